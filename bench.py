@@ -1,0 +1,144 @@
+"""Benchmark: ns per spin update of the Swendsen-Wang sweep on one MI355X.
+
+Default workload: q = 2 Potts (Ising) at T_c = 1/ln(1+sqrt 2), L = 4096,
+random start, 200 warm-up (thermalisation) sweeps, then the timed sweeps --
+the L = 4096 column of Table 1 (update only).  A "step" is one sweep of the
+whole hot path (bonds + labeling + flip) over the lattice resident in HBM.
+
+Prints one JSON line with the metric, a roofline object for the dominant
+kernel (algorithmic bytes per launch / HIP-event launch time) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, 8 TB/s
+PAPER_NS_PER_UPDATE = {"potts2_L4096_Tc": 2.51, "clock6_L4096_T0.9": 2.42}  # GTX580, Tables 1 and 3
+
+
+def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile_h: int = 64) -> float:
+    """Algorithmic HBM bytes of one launch (the method's own traffic, perf mode).
+
+    k_bond_local: spins read once (1 B/site) plus the halo column and row of
+      every tile (L*L*(1/tile_w + 1/tile_h) B), bonds written (2 bits/site =
+      0.25 B/site), labels written (4 B/site).
+    k_border_merge: per tile-border site, one bond word bit-read (counted as
+      1/8 B) and the two label words of its endpoints read (8 B).
+    k_flip: labels read (4 B/site), spins written (1 B/site); the clock model
+      also reads the old spin (1 B/site).
+    """
+    N = float(L) * L
+    if kernel == "k_bond_local":
+        return N * (1.0 + 1.0 / tile_w + 1.0 / tile_h + 0.25 + 4.0)
+    if kernel == "k_border_merge":
+        border = L * (-(-L // tile_w)) + L * (-(-L // tile_h))
+        return border * (0.125 + 8.0)
+    if kernel == "k_flip":
+        return N * (4.0 + 1.0 + (1.0 if model == "clock" else 0.0))
+    if kernel == "k_counts":
+        return N * (1.0 + 1.0 / tile_w + 1.0 / tile_h)
+    raise KeyError(kernel)
+
+
+def cpu_baseline(cfg, budget_s: float) -> dict:
+    """The oracle (single thread) on the first sweeps of the same workload."""
+    import oracle
+
+    ch = oracle.Chain(cfg.L, cfg.q, cfg.model, T=cfg.T, J=cfg.J, seed=cfg.seed)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        ch.sweep(1)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": dt * 1e9 / (n * cfg.L * cfg.L), "unit": "ns/spin-update", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} sweeps of {cfg.name} from the random start (single-threaded C oracle)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="potts2_L4096_Tc")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the single-lattice sweep "
+              "is not sharded across GPUs here.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1202_0635_amd as swmc
+    from paper_1202_0635_amd.workloads import CONFIGS
+
+    cfg = CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    N = cfg.L * cfg.L
+    lat = swmc.Lattice(cfg.L, cfg.q, cfg.model, T=cfg.T, J=cfg.J, seed=cfg.seed)
+    lat.sweep(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.sweep(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ns_per_update = ms * 1e6 / (args.steps * N)
+
+    # Per-kernel launch times over a second pass of the same number of sweeps.
+    lat.sweep(args.steps, profile=True)
+    prof = lat.profile()
+    kernels = {k: {"launches": n, "avg_us": 1e3 * t / n} for k, (n, t) in prof.items() if n}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    dom_bytes = alg_bytes_per_launch(dom, cfg.L, cfg.model)
+    achieved = dom_bytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+    sweep_bytes = sum(alg_bytes_per_launch(k, cfg.L, cfg.model) for k in ("k_bond_local", "k_border_merge", "k_flip"))
+    sweep_gbps = sweep_bytes / (ms * 1e-3 / args.steps) / 1e9
+
+    paper = PAPER_NS_PER_UPDATE.get(cfg.name)
+    out = {
+        "metric": "ns per spin update (SW sweep)",
+        "value": ns_per_update,
+        "unit": "ns/spin-update",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": (ns_per_update / paper) if paper else None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "L": cfg.L, "q": cfg.q, "model": cfg.model, "T": cfg.T, "J": cfg.J,
+                   "seed": cfg.seed, "warmup_sweeps": args.warmup, "timed_sweeps": args.steps},
+        "spin_updates_per_s": N * args.steps / (ms * 1e-3),
+        "sweep_alg_GBps": sweep_gbps,
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    lat.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,146 @@
+/*
+ * sw.h -- C-ABI of libswmc: the Swendsen-Wang multi-cluster sweep for 2D
+ * q-state Potts and q-state clock models on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Komura & Okabe, "GPU-based Swendsen-Wang multi-cluster algorithm
+ * for the simulation of two-dimensional classical spin systems"
+ * (arXiv:1202.0635).  One sweep has the three steps of Sec. 2:
+ *   (1) Fortuin-Kasteleyn bond activation between neighbours,
+ *   (2) connected-component labeling of the bond graph,
+ *   (3) a new random value (Potts) or a random reflection (clock, Wolff's
+ *       embedded cluster, Sec. 4) for every cluster.
+ *
+ * Every call returns an sw_status (0 = SW_OK, negative = error) and never
+ * throws.  Invalid parameters are rejected before any device work.  A device
+ * error is sticky: afterwards every call on that context returns SW_ESTATE
+ * until sw_free.  sw_last_error() gives a thread-local detail string for the
+ * last failing call of the calling thread.
+ *
+ * Determinism: the chain is a pure function of (sw_lattice, number of sweeps).
+ * All random numbers are Philox4x32-10 draws keyed by the seed, with the
+ * counter (index, sweep mod 2^32, purpose, sweep >> 32); bond thresholds come
+ * from a host FP64 table as uint32 cutoffs; the canonical label of a cluster
+ * is its smallest site index (Sec. 2: the proper label is the smallest).
+ * Results do not depend on tiling, batching or scheduling.
+ *
+ * Conventions: site i = y*L + x; spins are int8 in {0..q-1} (the paper's
+ * S = k+1 for Potts, angle 2 pi k / q for the clock model); site i owns its
+ * right bond to (x+1 mod L, y) and its down bond to (x, y+1 mod L).  Periodic
+ * boundaries (Sec. 2).
+ *
+ * Concurrency: one context per stream; a context is not thread-safe, distinct
+ * contexts are independent.
+ */
+#ifndef SW_H
+#define SW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_EINVAL = -1,   /* invalid argument (checked before any device work) */
+    SW_ENOMEM = -2,   /* device memory: allocation failed or caller buffer too small */
+    SW_EDEVICE = -3,  /* a HIP runtime call failed; the context becomes unusable */
+    SW_ESTATE = -4,   /* the context had a device error earlier, or a call came out of order */
+    SW_EBUDGET = -5,  /* (server) a request does not fit the memory budget */
+    SW_EBUSY = -6     /* (server) no free slot or result not ready */
+} sw_status;
+
+typedef enum { SW_POTTS = 0, SW_CLOCK = 1 } sw_model;
+
+/* flags of sw_sweep */
+enum {
+    SW_MEASURE = 1u, /* accumulate E, M^2, M^4 after every sweep of this call */
+    SW_VERIFY = 2u,  /* also store the canonical labels of the last sweep */
+    SW_PROFILE = 4u  /* time every kernel launch with HIP events (read by sw_profile_read) */
+};
+
+/* One lattice.  Potts: H = -J sum_<ij> (delta(S_i,S_j) - 1) (Sec. 2, Eq. 1);
+ * clock: H = -J sum_<ij> S_i . S_j with S = (cos 2 pi k/q, sin 2 pi k/q) (Sec. 4).
+ * Valid: 2 <= L <= 46340, 2 <= q <= 32, model in {SW_POTTS, SW_CLOCK},
+ * 0 < T, 0 < J (finite).  reserved must be 0. */
+typedef struct {
+    int32_t L, q, model, reserved;
+    double T, J;
+    uint64_t seed;
+} sw_lattice;
+
+/* Observables.  Integer fields are exact; doubles are derived on the host in
+ * FP64 in a fixed order.  e_per_site = H / N.  m2 = M^2 / N^2 with the Potts
+ * order parameter M^2 = (q sum_k n[k]^2 - N^2)/(q-1) (Sec. 4, equation after
+ * the moment ratio), or |M|^2 / N^2 for the clock model.  mean_* are running
+ * averages over the sweeps measured so far (SW_MEASURE); m4 is (M^2)^2 and
+ * binder_u = <M^4>/<M^2>^2 is the moment ratio of Sec. 4. */
+typedef struct {
+    uint64_t sweeps_done; /* sweep index t of the current state */
+    uint64_t samples;     /* number of measured sweeps accumulated */
+    int64_t hist[32];     /* n[k], number of sites in state k (k < q) */
+    int64_t pair_hist[32];/* owned bonds (2N) by (s_j - s_i) mod q */
+    double e_per_site, m2;
+    double mean_e, mean_m2, mean_m4, binder_u;
+} sw_obs;
+
+typedef struct sw_ctx sw_ctx;
+
+/* Device bytes needed for one lattice (arena for sw_init); 0 if *p is invalid. */
+size_t sw_state_bytes(const sw_lattice* p);
+
+/* Create a context and the random start (s_i = qmap(Philox(i, 0, init)), t = 0).
+ * dev_mem: caller-owned device buffer of at least sw_state_bytes(p) bytes,
+ *          256-byte aligned, which the context uses and never frees; or NULL,
+ *          in which case the library allocates (and sw_free releases) it.
+ * stream:  hipStream_t (NULL = the null stream); every kernel of this context
+ *          runs on it, and calls that return data synchronise it.
+ * Errors: SW_EINVAL (bad parameters, unaligned or short buffer), SW_ENOMEM,
+ *         SW_EDEVICE.  On error *out is NULL. */
+int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_ctx** out);
+
+/* Run nsweeps >= 0 sweeps (Sec. 2 steps (1)-(3), Sec. 3 for the GPU), enqueued
+ * asynchronously on the stream.  flags: SW_MEASURE | SW_VERIFY | SW_PROFILE.
+ * With SW_MEASURE the call synchronises every 1024 sweeps and at its end to
+ * fold the per-sweep counts into the running averages. */
+int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags);
+
+/* Observables of the current state plus the running averages (synchronises). */
+int sw_measure(sw_ctx* c, sw_obs* out);
+
+/* Synchronous copies to host memory.  n must equal N = L*L (SW_EINVAL otherwise).
+ * sw_read_labels returns the canonical labels (smallest site index of the
+ * cluster) of the last sweep run with SW_VERIFY (SW_ESTATE if there was none).
+ * sw_read_bonds returns one byte (0/1) per site for the right and down bonds of
+ * the last sweep. */
+int sw_read_spins(sw_ctx* c, int8_t* host, size_t n);
+int sw_read_labels(sw_ctx* c, int32_t* host, size_t n);
+int sw_read_bonds(sw_ctx* c, uint8_t* host_right, uint8_t* host_down, size_t n);
+
+/* Replace the state (restore / tests): spins host[n] with values < q
+ * (SW_EINVAL otherwise) and the sweep index t.  Synchronous. */
+int sw_write_spins(sw_ctx* c, const int8_t* host, size_t n, uint64_t t);
+
+/* Device address of the spin array (int8[N], row-major) owned by the context. */
+int sw_device_spins(sw_ctx* c, void** dev_ptr);
+
+/* Host-only: the uint32 cutoff table of the bond rule (Sec. 2 step (ii); Sec. 4
+ * embedded cluster).  Potts: q*q entries C[a*q+b]; clock: q^3 entries
+ * C[(m*q+a)*q+b].  n must equal that size.  Needs no GPU. */
+int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n);
+
+/* Per-kernel timing of the sweeps run with SW_PROFILE since the last read:
+ * names[k] (static strings), launches[k], total_ms[k] for k < *nk (at most
+ * cap).  Synchronises.  Resets the accumulators. */
+int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* total_ms,
+                    int32_t cap, int32_t* nk);
+
+void sw_free(sw_ctx* c);
+const char* sw_strerror(int status);
+const char* sw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_H */

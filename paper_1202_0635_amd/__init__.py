@@ -1,0 +1,153 @@
+"""MI355X-native Swendsen-Wang multi-cluster sweep for 2D Potts and clock models.
+
+Method: Komura & Okabe, arXiv:1202.0635 -- Sec. 2 (the three SW steps), Sec. 3
+(cluster labeling on a GPU), Sec. 4 (clock model via embedded clusters,
+observables M^2 and the moment ratio).  The sweep runs in hand-written HIP
+kernels of libswmc.so (include/sw.h); this module only marshals arguments.
+PyTorch provides device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import _lib
+from ._lib import SW_CLOCK, SW_MEASURE, SW_POTTS, SW_PROFILE, SW_VERIFY, SwError, SwLattice, SwObs, check
+
+__all__ = ["Lattice", "SwError", "critical_temperature", "cutoff_table", "state_bytes",
+           "SW_MEASURE", "SW_VERIFY", "SW_PROFILE"]
+
+MODELS = {"potts": SW_POTTS, "clock": SW_CLOCK}
+
+
+def critical_temperature(model: str, q: int) -> float:
+    """Potts: T_c/J = 1/ln(1+sqrt q) (Sec. 4, printed for q = 2, 3).  Clock q = 6:
+    the upper KT temperature T_2/J ~ 0.9 quoted in Sec. 4."""
+    if model == "potts":
+        return 1.0 / math.log(1.0 + math.sqrt(q))
+    if model == "clock" and q == 6:
+        return 0.9
+    raise ValueError("no critical temperature for this model/q")
+
+
+def _lattice(L, q, model, T, J, seed) -> SwLattice:
+    m = MODELS[model] if isinstance(model, str) else int(model)
+    return SwLattice(int(L), int(q), m, 0, float(T), float(J), int(seed) & (2**64 - 1))
+
+
+def state_bytes(L, q, model="potts", T=1.0, J=1.0, seed=0) -> int:
+    return int(_lib.lib().sw_state_bytes(ctypes.byref(_lattice(L, q, model, T, J, seed))))
+
+
+def cutoff_table(L, q, model="potts", T=1.0, J=1.0) -> np.ndarray:
+    """The host FP64 -> uint32 cutoff table of the bond rule (no GPU needed)."""
+    p = _lattice(L, q, model, T, J, 0)
+    n = q * q if p.model == SW_POTTS else q * q * q
+    out = np.zeros(n, dtype=np.uint32)
+    check(_lib.lib().sw_cutoff_table(ctypes.byref(p), out.ctypes.data_as(ctypes.c_void_p), n), "sw_cutoff_table")
+    return out
+
+
+class Lattice:
+    """One L x L periodic lattice resident in device memory.
+
+    Device memory is a torch uint8 tensor on the current CUDA (HIP) device; the
+    kernels run on the current torch stream at construction time."""
+
+    def __init__(self, L: int, q: int, model: str = "potts", T: float | None = None, J: float = 1.0,
+                 seed: int = 0, device=None, stream=None):
+        import torch
+
+        if T is None:
+            T = critical_temperature(model, q)
+        self.L, self.q, self.model, self.T, self.J, self.seed = int(L), int(q), model, float(T), float(J), int(seed)
+        self._p = _lattice(L, q, model, T, J, seed)
+        lib = _lib.lib()
+        nbytes = int(lib.sw_state_bytes(ctypes.byref(self._p)))
+        if nbytes == 0:
+            check(_lib.SW_EINVAL, "sw_state_bytes")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._arena.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            check(lib.sw_init(ctypes.byref(self._p), ctypes.c_void_p(aligned), nbytes,
+                              ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx)), "sw_init")
+        self._ctx = ctx
+        self.N = self.L * self.L
+
+    # -- sweeps ------------------------------------------------------------
+    def sweep(self, n: int = 1, measure: bool = False, verify: bool = False, profile: bool = False):
+        flags = (SW_MEASURE if measure else 0) | (SW_VERIFY if verify else 0) | (SW_PROFILE if profile else 0)
+        check(_lib.lib().sw_sweep(self._ctx, int(n), flags), "sw_sweep")
+        return self
+
+    def measure(self) -> dict:
+        o = SwObs()
+        check(_lib.lib().sw_measure(self._ctx, ctypes.byref(o)), "sw_measure")
+        return {
+            "t": int(o.sweeps_done), "samples": int(o.samples),
+            "hist": np.array(o.hist[: self.q], dtype=np.int64),
+            "pair_hist": np.array(o.pair_hist[: self.q], dtype=np.int64),
+            "e": o.e_per_site, "m2": o.m2, "mean_e": o.mean_e, "mean_m2": o.mean_m2,
+            "mean_m4": o.mean_m4, "binder_u": o.binder_u,
+        }
+
+    # -- state ---------------------------------------------------------------
+    def spins(self) -> np.ndarray:
+        out = np.zeros(self.N, dtype=np.int8)
+        check(_lib.lib().sw_read_spins(self._ctx, out.ctypes.data_as(ctypes.c_void_p), self.N), "sw_read_spins")
+        return out.reshape(self.L, self.L)
+
+    def labels(self) -> np.ndarray:
+        out = np.zeros(self.N, dtype=np.int32)
+        check(_lib.lib().sw_read_labels(self._ctx, out.ctypes.data_as(ctypes.c_void_p), self.N), "sw_read_labels")
+        return out.reshape(self.L, self.L)
+
+    def bonds(self):
+        r = np.zeros(self.N, dtype=np.uint8)
+        d = np.zeros(self.N, dtype=np.uint8)
+        check(_lib.lib().sw_read_bonds(self._ctx, r.ctypes.data_as(ctypes.c_void_p),
+                                       d.ctypes.data_as(ctypes.c_void_p), self.N), "sw_read_bonds")
+        return r.reshape(self.L, self.L), d.reshape(self.L, self.L)
+
+    def set_spins(self, spins, t: int = 0):
+        s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
+        check(_lib.lib().sw_write_spins(self._ctx, s.ctypes.data_as(ctypes.c_void_p), s.size, int(t)),
+              "sw_write_spins")
+        return self
+
+    def spins_device(self):
+        """torch int8 view [L, L] of the device spin array (no copy)."""
+        import torch
+
+        ptr = ctypes.c_void_p()
+        check(_lib.lib().sw_device_spins(self._ctx, ctypes.byref(ptr)), "sw_device_spins")
+        off = ptr.value - self._arena.data_ptr()
+        return self._arena[off: off + self.N].view(torch.int8).view(self.L, self.L)
+
+    def profile(self) -> dict:
+        names = (ctypes.c_char_p * 8)()
+        launches = (ctypes.c_int64 * 8)()
+        ms = (ctypes.c_double * 8)()
+        nk = ctypes.c_int32()
+        check(_lib.lib().sw_profile_read(self._ctx, names, launches, ms, 8, ctypes.byref(nk)), "sw_profile_read")
+        return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(nk.value)}
+
+    def synchronize(self):
+        self._stream.synchronize()
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.lib().sw_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,92 @@
+"""ctypes declarations of libswmc (include/sw.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libswmc.so")
+
+SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_ESTATE, SW_EBUDGET, SW_EBUSY = 0, -1, -2, -3, -4, -5, -6
+SW_POTTS, SW_CLOCK = 0, 1
+SW_MEASURE, SW_VERIFY, SW_PROFILE = 1, 2, 4
+
+
+class SwLattice(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("model", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("T", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class SwObs(ctypes.Structure):
+    _fields_ = [
+        ("sweeps_done", ctypes.c_uint64),
+        ("samples", ctypes.c_uint64),
+        ("hist", ctypes.c_int64 * 32),
+        ("pair_hist", ctypes.c_int64 * 32),
+        ("e_per_site", ctypes.c_double),
+        ("m2", ctypes.c_double),
+        ("mean_e", ctypes.c_double),
+        ("mean_m2", ctypes.c_double),
+        ("mean_m4", ctypes.c_double),
+        ("binder_u", ctypes.c_double),
+    ]
+
+
+class SwError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes); every exported symbol of include/sw.h
+SIGNATURES = {
+    "sw_state_bytes": (ctypes.c_size_t, [ctypes.POINTER(SwLattice)]),
+    "sw_init": (ctypes.c_int, [ctypes.POINTER(SwLattice), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
+    "sw_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwObs)]),
+    "sw_read_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_read_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_read_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_write_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64]),
+    "sw_device_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_cutoff_table": (ctypes.c_int, [ctypes.POINTER(SwLattice), ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "sw_free": (None, [ctypes.c_void_p]),
+    "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sw_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_1202_0635_amd.build, or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str) -> None:
+    if status != SW_OK:
+        detail = lib().sw_last_error().decode(errors="replace")
+        raise SwError(status, where, detail or lib().sw_strerror(status).decode())

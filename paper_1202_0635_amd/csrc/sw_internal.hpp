@@ -1,0 +1,65 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libswmc.  Nothing here crosses the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swmc {
+
+// Tile of the bond + local-labeling kernel: 64 columns (one per lane of a
+// wave64) by kTileH rows; a workgroup of 4 waves, each wave owning
+// kTileH / 4 consecutive rows.
+constexpr int kTileW = 64;
+constexpr int kTileH = 64;
+constexpr int kWaves = 4;
+constexpr int kBlock = kWaves * 64;
+
+// Random-number purposes (third counter word of a Philox draw).
+constexpr uint32_t kBondHi = 0;
+constexpr uint32_t kBondLo = 1;
+constexpr uint32_t kCluster = 2;
+constexpr uint32_t kMirror = 3;
+constexpr uint32_t kInit = 4;
+
+// Root marker in the label array: a word with this bit set belongs to a
+// cluster root and carries the cluster's draw (Potts: new value; clock: the
+// reflection bit) in its low bits; any other word is the index of a site of
+// the same cluster with a smaller index.
+constexpr uint32_t kRootFlag = 0x80000000u;
+
+constexpr int kRing = 1024;      // per-sweep count rows kept on the device
+constexpr int kRowWords = 64;    // int64 per count row: hist[32], pair_hist[32]
+
+// Device control block at the start of the arena.
+struct Control {
+    uint64_t t;       // sweep index of the current state
+    uint32_t done;    // finished-workgroup counter of the flip kernel
+    uint32_t pad[13];
+};
+
+struct SweepArgs {
+    int8_t* spins;        // [N]
+    uint64_t* bond_r;     // [L][w64]: bit x%64 of word x/64 = right bond of (x,y)
+    uint64_t* bond_d;     // [L][w64]: down bonds
+    uint32_t* labels;     // [N] union-find forest with root words (kRootFlag)
+    uint32_t* canon;      // [N] canonical labels (verify mode)
+    const uint32_t* table;// cutoff table (Potts q*q; clock q^3)
+    Control* ctl;
+    int64_t* count_row;   // destination row of the count kernel (or null)
+    int L, q, model, w64;
+    int tiles_x, tiles_y;
+    uint32_t key0, key1;
+};
+
+// Launch wrappers (defined in sw_kernels.hip).
+hipError_t launch_init(const SweepArgs& a, hipStream_t s);
+hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s);
+hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
+hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s);
+hipError_t launch_counts(const SweepArgs& a, hipStream_t s);
+
+enum KernelId { kKBondLocal = 0, kKBorderMerge = 1, kKFlip = 2, kKCounts = 3, kNumKernels = 4 };
+extern const char* const kKernelNames[kNumKernels];
+
+}  // namespace swmc

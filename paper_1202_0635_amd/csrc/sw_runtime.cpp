@@ -1,0 +1,525 @@
+// Host runtime of libswmc: parameter checks, the FP64 cutoff table, the
+// device arena, kernel sequencing and the C-ABI of include/sw.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sw.h"
+#include "sw_internal.hpp"
+
+using namespace swmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+bool lattice_ok(const sw_lattice* p, std::string* why) {
+    if (!p) return *why = "null sw_lattice", false;
+    if (p->L < 2 || p->L > 46340) return *why = "L must be in [2, 46340]", false;
+    if (p->q < 2 || p->q > 32) return *why = "q must be in [2, 32]", false;
+    if (p->model != SW_POTTS && p->model != SW_CLOCK) return *why = "model must be SW_POTTS or SW_CLOCK", false;
+    if (p->reserved != 0) return *why = "reserved must be 0", false;
+    if (!(p->T > 0.0) || !std::isfinite(p->T)) return *why = "T must be positive and finite", false;
+    if (!(p->J > 0.0) || !std::isfinite(p->J)) return *why = "J must be positive and finite", false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Cutoff table (Sec. 2 step (ii); Sec. 4 embedded cluster).  A bond is active
+// iff its 32-bit uniform u < C, C = floor(2^32 p) with p = -expm1(-x) in FP64.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+
+// cos / sin of the angle 2 pi n / q; angles that are multiples of 30 degrees
+// with a rational cosine (sine) are exact, the rest come from libm.
+double turn_cos(int n, int q) {
+    n = ((n % q) + q) % q;
+    if ((12 * n) % q == 0) {
+        static const double exact[12] = {1.0, NAN, 0.5, 0.0, -0.5, NAN, -1.0, NAN, -0.5, 0.0, 0.5, NAN};
+        const double v = exact[(12 * n) / q];
+        if (!std::isnan(v)) return v;
+    }
+    return std::cos(2.0 * kPi * static_cast<double>(n) / static_cast<double>(q));
+}
+
+double turn_sin(int n, int q) {
+    n = ((n % q) + q) % q;
+    if ((12 * n) % q == 0) {
+        static const double exact[12] = {0.0, 0.5, NAN, 1.0, NAN, 0.5, 0.0, -0.5, NAN, -1.0, NAN, -0.5};
+        const double v = exact[(12 * n) / q];
+        if (!std::isnan(v)) return v;
+    }
+    return std::sin(2.0 * kPi * static_cast<double>(n) / static_cast<double>(q));
+}
+
+uint32_t cutoff(double x) {
+    const double c = std::floor(std::ldexp(-std::expm1(-x), 32));
+    if (c >= 4294967295.0) return 0xFFFFFFFFu;
+    if (c <= 0.0) return 0u;
+    return static_cast<uint32_t>(c);
+}
+
+size_t table_entries(const sw_lattice& p) {
+    return p.model == SW_POTTS ? static_cast<size_t>(p.q) * p.q : static_cast<size_t>(p.q) * p.q * p.q;
+}
+
+void build_table(const sw_lattice& p, uint32_t* out) {
+    const int q = p.q;
+    if (p.model == SW_POTTS) {
+        const uint32_t c = cutoff(p.J / p.T);
+        for (int s = 0; s < q; ++s)
+            for (int u = 0; u < q; ++u) out[s * q + u] = (s == u) ? c : 0u;
+        return;
+    }
+    // Mirror m reflects state k to (m - k) mod q; the projection of two states
+    // on the mirror normal multiplies to [cos(a-b) - cos(a+b-m)] / 2 (angles in
+    // units of 2 pi / q); only positive products can bond, with x = 2 J P / T.
+    for (int m = 0; m < q; ++m)
+        for (int s = 0; s < q; ++s)
+            for (int u = 0; u < q; ++u) {
+                const double P = 0.5 * (turn_cos(s - u, q) - turn_cos(s + u - m, q));
+                out[(static_cast<size_t>(m) * q + s) * q + u] = P > 0.0 ? cutoff(2.0 * p.J * P / p.T) : 0u;
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Device arena layout.
+// ---------------------------------------------------------------------------
+constexpr size_t kAlign = 256;
+size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t ctl, spins, bond_r, bond_d, labels, canon, ring, scratch_row, table, total;
+};
+
+Layout layout_of(const sw_lattice& p) {
+    const size_t L = static_cast<size_t>(p.L);
+    const size_t N = L * L;
+    const size_t w64 = (L + 63) / 64;
+    Layout l{};
+    size_t o = 0;
+    l.ctl = o; o += up(sizeof(Control));
+    l.spins = o; o += up(N);
+    l.bond_r = o; o += up(L * w64 * 8);
+    l.bond_d = o; o += up(L * w64 * 8);
+    l.labels = o; o += up(N * 4);
+    l.canon = o; o += up(N * 4);
+    l.ring = o; o += up(static_cast<size_t>(kRing) * kRowWords * 8);
+    l.scratch_row = o; o += up(kRowWords * 8);
+    l.table = o; o += up(table_entries(p) * 4);
+    l.total = o;
+    return l;
+}
+
+struct Observables {
+    double e = 0.0, m2 = 0.0;
+};
+
+Observables observables_of(const sw_lattice& p, const int64_t* row) {
+    const double N = static_cast<double>(p.L) * static_cast<double>(p.L);
+    const int q = p.q;
+    const int64_t* hist = row;
+    const int64_t* pair = row + 32;
+    Observables o;
+    if (p.model == SW_POTTS) {
+        o.e = p.J * (2.0 * N - static_cast<double>(pair[0])) / N;
+        double s2 = 0.0;
+        for (int k = 0; k < q; ++k) s2 += static_cast<double>(hist[k]) * static_cast<double>(hist[k]);
+        o.m2 = (static_cast<double>(q) * s2 - N * N) / (static_cast<double>(q - 1) * N * N);
+    } else {
+        double e = 0.0;
+        for (int d = 0; d < q; ++d) e += static_cast<double>(pair[d]) * turn_cos(d, q);
+        o.e = -p.J * e / N;
+        double mx = 0.0, my = 0.0;
+        for (int k = 0; k < q; ++k) {
+            mx += static_cast<double>(hist[k]) * turn_cos(k, q);
+            my += static_cast<double>(hist[k]) * turn_sin(k, q);
+        }
+        o.m2 = (mx * mx + my * my) / (N * N);
+    }
+    return o;
+}
+
+}  // namespace
+
+struct sw_ctx {
+    sw_lattice p{};
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    bool owns = false;
+    bool sticky = false;
+    bool have_canon = false;
+    Layout lay{};
+    SweepArgs args{};
+    std::vector<uint32_t> table;
+    // running averages over measured sweeps
+    uint64_t samples = 0;
+    double sum_e = 0.0, sum_m2 = 0.0, sum_m4 = 0.0;
+    std::vector<int64_t> ring_host;
+    // per-kernel timing
+    std::vector<hipEvent_t> free_events;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    int64_t prof_launches[kNumKernels] = {0, 0, 0, 0};
+    double prof_ms[kNumKernels] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int device_fail(sw_ctx* c, hipError_t e, const char* what) {
+    if (c) c->sticky = true;
+    return fail(SW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SW_HIP(ctx, call)                                      \
+    do {                                                      \
+        const hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return device_fail(ctx, e_, #call); \
+    } while (0)
+
+hipEvent_t take_event(sw_ctx* c) {
+    if (!c->free_events.empty()) {
+        hipEvent_t e = c->free_events.back();
+        c->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch one kernel of the sweep, optionally bracketed by timing events.
+template <typename F>
+int timed(sw_ctx* c, bool profile, int kid, F&& launch) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (profile) {
+        e0 = take_event(c);
+        e1 = take_event(c);
+        if (!e0 || !e1) return device_fail(c, hipErrorOutOfMemory, "hipEventCreate");
+        SW_HIP(c, hipEventRecord(e0, c->stream));
+    }
+    SW_HIP(c, launch());
+    if (profile) {
+        SW_HIP(c, hipEventRecord(e1, c->stream));
+        c->pending.push_back({kid, {e0, e1}});
+    }
+    return SW_OK;
+}
+
+int check_ctx(sw_ctx* c) {
+    if (!c) return fail(SW_EINVAL, "null context");
+    if (c->sticky) return fail(SW_ESTATE, "context had a device error earlier");
+    return SW_OK;
+}
+
+// Fold count rows [0, rows) of the device ring into the running averages.
+int flush_ring(sw_ctx* c, int rows) {
+    if (rows <= 0) return SW_OK;
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    c->ring_host.resize(static_cast<size_t>(rows) * kRowWords);
+    SW_HIP(c, hipMemcpy(c->ring_host.data(), c->base + c->lay.ring, c->ring_host.size() * 8, hipMemcpyDeviceToHost));
+    for (int r = 0; r < rows; ++r) {
+        const Observables o = observables_of(c->p, c->ring_host.data() + static_cast<size_t>(r) * kRowWords);
+        c->sum_e += o.e;
+        c->sum_m2 += o.m2;
+        c->sum_m4 += o.m2 * o.m2;
+        c->samples += 1;
+    }
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sw_state_bytes(const sw_lattice* p) {
+    std::string why;
+    if (!lattice_ok(p, &why)) {
+        fail(SW_EINVAL, "%s", why.c_str());
+        return 0;
+    }
+    return layout_of(*p).total;
+}
+
+int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n) {
+    std::string why;
+    if (!lattice_ok(p, &why)) return fail(SW_EINVAL, "%s", why.c_str());
+    if (!out || n != table_entries(*p)) return fail(SW_EINVAL, "table size must be %zu", table_entries(*p));
+    build_table(*p, out);
+    return SW_OK;
+}
+
+int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_ctx** out) {
+    if (!out) return fail(SW_EINVAL, "null output pointer");
+    *out = nullptr;
+    std::string why;
+    if (!lattice_ok(p, &why)) return fail(SW_EINVAL, "%s", why.c_str());
+    const Layout lay = layout_of(*p);
+    if (dev_mem) {
+        if (reinterpret_cast<uintptr_t>(dev_mem) % kAlign != 0) return fail(SW_EINVAL, "dev_mem must be 256-byte aligned");
+        if (bytes < lay.total) return fail(SW_ENOMEM, "dev_mem has %zu bytes, need %zu", bytes, lay.total);
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SW_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail(SW_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SW_EDEVICE, "libswmc is built for gfx950; device %d is %s", dev, prop.gcnArchName);
+
+    sw_ctx* c = new sw_ctx();
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->lay = lay;
+    if (dev_mem) {
+        c->base = static_cast<char*>(dev_mem);
+    } else {
+        void* m = nullptr;
+        e = hipMalloc(&m, lay.total);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(SW_ENOMEM, "hipMalloc(%zu): %s", lay.total, hipGetErrorString(e));
+        }
+        c->base = static_cast<char*>(m);
+        c->owns = true;
+    }
+    c->table.resize(table_entries(*p));
+    build_table(*p, c->table.data());
+
+    SweepArgs& a = c->args;
+    a.spins = reinterpret_cast<int8_t*>(c->base + lay.spins);
+    a.bond_r = reinterpret_cast<uint64_t*>(c->base + lay.bond_r);
+    a.bond_d = reinterpret_cast<uint64_t*>(c->base + lay.bond_d);
+    a.labels = reinterpret_cast<uint32_t*>(c->base + lay.labels);
+    a.canon = reinterpret_cast<uint32_t*>(c->base + lay.canon);
+    a.table = reinterpret_cast<const uint32_t*>(c->base + lay.table);
+    a.ctl = reinterpret_cast<Control*>(c->base + lay.ctl);
+    a.count_row = nullptr;
+    a.L = p->L;
+    a.q = p->q;
+    a.model = p->model;
+    a.w64 = (p->L + 63) / 64;
+    a.tiles_x = (p->L + kTileW - 1) / kTileW;
+    a.tiles_y = (p->L + kTileH - 1) / kTileH;
+    a.key0 = static_cast<uint32_t>(p->seed);
+    a.key1 = static_cast<uint32_t>(p->seed >> 32);
+
+    auto cleanup = [&](int st) {
+        if (c->owns) (void)hipFree(c->base);
+        delete c;
+        return st;
+    };
+    e = hipMemsetAsync(c->base + lay.ctl, 0, sizeof(Control), c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->base + lay.table, c->table.data(), c->table.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_init(a, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return cleanup(fail(SW_EDEVICE, "sw_init: %s", hipGetErrorString(e)));
+    *out = c;
+    return SW_OK;
+}
+
+int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
+    int st = check_ctx(c);
+    if (st) return st;
+    if (nsweeps < 0) return fail(SW_EINVAL, "nsweeps must be >= 0");
+    if (flags & ~(SW_MEASURE | SW_VERIFY | SW_PROFILE)) return fail(SW_EINVAL, "unknown flag bits");
+    const bool measure = flags & SW_MEASURE;
+    const bool profile = flags & SW_PROFILE;
+    int rows = 0;
+    for (int32_t s = 0; s < nsweeps; ++s) {
+        const bool verify = (flags & SW_VERIFY) && (s == nsweeps - 1);
+        if (measure && rows == 0) {
+            const int chunk = (nsweeps - s < kRing) ? (nsweeps - s) : kRing;
+            SW_HIP(c, hipMemsetAsync(c->base + c->lay.ring, 0, static_cast<size_t>(chunk) * kRowWords * 8, c->stream));
+        }
+        st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(c->args, c->stream); });
+        if (st) return st;
+        st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(c->args, c->stream); });
+        if (st) return st;
+        st = timed(c, profile, kKFlip, [&] { return launch_flip(c->args, verify, c->stream); });
+        if (st) return st;
+        if (verify) c->have_canon = true;
+        if (measure) {
+            SweepArgs a = c->args;
+            a.count_row = reinterpret_cast<int64_t*>(c->base + c->lay.ring) + static_cast<size_t>(rows) * kRowWords;
+            st = timed(c, profile, kKCounts, [&] { return launch_counts(a, c->stream); });
+            if (st) return st;
+            if (++rows == kRing) {
+                st = flush_ring(c, rows);
+                if (st) return st;
+                rows = 0;
+            }
+        }
+    }
+    return flush_ring(c, rows);
+}
+
+int sw_measure(sw_ctx* c, sw_obs* out) {
+    int st = check_ctx(c);
+    if (st) return st;
+    if (!out) return fail(SW_EINVAL, "null sw_obs");
+    SweepArgs a = c->args;
+    a.count_row = reinterpret_cast<int64_t*>(c->base + c->lay.scratch_row);
+    SW_HIP(c, hipMemsetAsync(a.count_row, 0, kRowWords * 8, c->stream));
+    SW_HIP(c, launch_counts(a, c->stream));
+    int64_t row[kRowWords];
+    Control ctl;
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    SW_HIP(c, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
+    SW_HIP(c, hipMemcpy(&ctl, c->base + c->lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    out->sweeps_done = ctl.t;
+    out->samples = c->samples;
+    for (int k = 0; k < 32; ++k) {
+        out->hist[k] = row[k];
+        out->pair_hist[k] = row[32 + k];
+    }
+    const Observables o = observables_of(c->p, row);
+    out->e_per_site = o.e;
+    out->m2 = o.m2;
+    if (c->samples) {
+        const double n = static_cast<double>(c->samples);
+        out->mean_e = c->sum_e / n;
+        out->mean_m2 = c->sum_m2 / n;
+        out->mean_m4 = c->sum_m4 / n;
+        out->binder_u = out->mean_m2 > 0.0 ? out->mean_m4 / (out->mean_m2 * out->mean_m2) : 0.0;
+    }
+    return SW_OK;
+}
+
+int sw_read_spins(sw_ctx* c, int8_t* host, size_t n) {
+    int st = check_ctx(c);
+    if (st) return st;
+    const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
+    if (!host || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    SW_HIP(c, hipMemcpy(host, c->base + c->lay.spins, N, hipMemcpyDeviceToHost));
+    return SW_OK;
+}
+
+int sw_read_labels(sw_ctx* c, int32_t* host, size_t n) {
+    int st = check_ctx(c);
+    if (st) return st;
+    const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
+    if (!host || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
+    if (!c->have_canon) return fail(SW_ESTATE, "no sweep was run with SW_VERIFY");
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    SW_HIP(c, hipMemcpy(host, c->base + c->lay.canon, N * 4, hipMemcpyDeviceToHost));
+    return SW_OK;
+}
+
+int sw_read_bonds(sw_ctx* c, uint8_t* host_right, uint8_t* host_down, size_t n) {
+    int st = check_ctx(c);
+    if (st) return st;
+    const size_t L = static_cast<size_t>(c->p.L);
+    const size_t N = L * L;
+    if (!host_right || !host_down || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
+    const size_t w64 = static_cast<size_t>(c->args.w64);
+    std::vector<uint64_t> r(L * w64), d(L * w64);
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    SW_HIP(c, hipMemcpy(r.data(), c->base + c->lay.bond_r, r.size() * 8, hipMemcpyDeviceToHost));
+    SW_HIP(c, hipMemcpy(d.data(), c->base + c->lay.bond_d, d.size() * 8, hipMemcpyDeviceToHost));
+    for (size_t y = 0; y < L; ++y)
+        for (size_t x = 0; x < L; ++x) {
+            host_right[y * L + x] = static_cast<uint8_t>((r[y * w64 + x / 64] >> (x % 64)) & 1u);
+            host_down[y * L + x] = static_cast<uint8_t>((d[y * w64 + x / 64] >> (x % 64)) & 1u);
+        }
+    return SW_OK;
+}
+
+int sw_write_spins(sw_ctx* c, const int8_t* host, size_t n, uint64_t t) {
+    int st = check_ctx(c);
+    if (st) return st;
+    const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
+    if (!host || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
+    for (size_t i = 0; i < N; ++i)
+        if (host[i] < 0 || host[i] >= c->p.q) return fail(SW_EINVAL, "spin %zu = %d is not in [0, q)", i, host[i]);
+    Control ctl{};
+    ctl.t = t;
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    SW_HIP(c, hipMemcpy(c->base + c->lay.spins, host, N, hipMemcpyHostToDevice));
+    SW_HIP(c, hipMemcpy(c->base + c->lay.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice));
+    c->have_canon = false;
+    return SW_OK;
+}
+
+int sw_device_spins(sw_ctx* c, void** dev_ptr) {
+    int st = check_ctx(c);
+    if (st) return st;
+    if (!dev_ptr) return fail(SW_EINVAL, "null output pointer");
+    *dev_ptr = c->base + c->lay.spins;
+    return SW_OK;
+}
+
+int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* total_ms, int32_t cap, int32_t* nk) {
+    int st = check_ctx(c);
+    if (st) return st;
+    if (!nk || cap < 0 || (cap > 0 && (!names || !launches || !total_ms))) return fail(SW_EINVAL, "bad output arrays");
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& pe : c->pending) {
+        float ms = 0.0f;
+        SW_HIP(c, hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+        c->prof_ms[pe.first] += ms;
+        c->prof_launches[pe.first] += 1;
+        c->free_events.push_back(pe.second.first);
+        c->free_events.push_back(pe.second.second);
+    }
+    c->pending.clear();
+    const int k = cap < kNumKernels ? cap : kNumKernels;
+    for (int i = 0; i < k; ++i) {
+        names[i] = kKernelNames[i];
+        launches[i] = c->prof_launches[i];
+        total_ms[i] = c->prof_ms[i];
+    }
+    *nk = k;
+    for (int i = 0; i < kNumKernels; ++i) {
+        c->prof_launches[i] = 0;
+        c->prof_ms[i] = 0.0;
+    }
+    return SW_OK;
+}
+
+void sw_free(sw_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& pe : c->pending) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
+    if (c->owns) (void)hipFree(c->base);
+    delete c;
+}
+
+const char* sw_strerror(int s) {
+    switch (s) {
+        case SW_OK: return "ok";
+        case SW_EINVAL: return "invalid argument";
+        case SW_ENOMEM: return "out of device memory";
+        case SW_EDEVICE: return "device error";
+        case SW_ESTATE: return "invalid state";
+        case SW_EBUDGET: return "over memory budget";
+        case SW_EBUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+const char* sw_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+"""GPU parity: the HIP sweep against the CPU oracle, element by element.
+
+Bonds, canonical labels and spins must be bit-identical after every sweep
+(the chain is a pure function of parameters and seed); counts are integers
+and must be identical; E, M^2, M^4 and the moment ratio agree to 1e-12
+relative (they are computed from identical integer counts).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TC2 = 1.0 / math.log(1.0 + math.sqrt(2.0))
+TC3 = 1.0 / math.log(1.0 + math.sqrt(3.0))
+TC4 = 1.0 / math.log(3.0)
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def swmc():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    import paper_1202_0635_amd as swmc
+
+    swmc._lib.lib()  # fail loudly if the HIP library was not built
+    return swmc
+
+
+CASES = [
+    # L, q, model, T, seed, sweeps
+    (64, 2, "potts", TC2, 1, 6),       # Ising L = 64 at T_c
+    (100, 3, "potts", TC3, 7, 5),      # ragged tiles
+    (130, 6, "clock", 0.9, 3, 5),      # ragged clock
+    (2, 2, "potts", TC2, 5, 8),        # multigraph torus
+    (3, 3, "potts", 0.7, 9, 8),
+    (5, 6, "clock", 0.6, 4, 8),
+    (63, 4, "potts", TC4, 11, 4),
+    (65, 2, "clock", 1.2, 12, 4),
+    (127, 2, "potts", 0.5, 13, 4),     # ordered: wrapped spanning clusters
+    (200, 2, "potts", 5.0, 14, 3),     # disordered: many small clusters
+    (192, 32, "potts", 0.4, 15, 3),    # q at the upper limit
+    (97, 32, "clock", 0.05, 16, 3),    # large q clock, cold
+    (256, 6, "clock", 0.9, 17, 3),
+]
+
+
+@pytest.mark.parametrize("L,q,model,T,seed,nsw", CASES)
+def test_sweep_parity(swmc, orc, L, q, model, T, seed, nsw):
+    _say(f"[parity] L={L} q={q} {model} T={T:.4f} seed={seed}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=seed)
+    ch = orc.Chain(L, q, model, T=T, seed=seed)
+    assert np.array_equal(lat.spins().reshape(-1), ch.spins), "random start differs"
+    for s in range(nsw):
+        lat.sweep(1, verify=True)
+        ch.sweep(1)
+        br, bd = lat.bonds()
+        assert np.array_equal(br.reshape(-1), ch.bond_r), f"right bonds differ at sweep {s}"
+        assert np.array_equal(bd.reshape(-1), ch.bond_d), f"down bonds differ at sweep {s}"
+        assert np.array_equal(lat.labels().reshape(-1), ch.labels), f"labels differ at sweep {s}"
+        assert np.array_equal(lat.spins().reshape(-1), ch.spins), f"spins differ at sweep {s}"
+    lat.close()
+
+
+@pytest.mark.parametrize("L,q,model,T", [(96, 3, "potts", TC3), (77, 6, "clock", 0.9)])
+def test_parity_from_arbitrary_state(swmc, orc, L, q, model, T):
+    from paper_1202_0635_amd.workloads import random_spins, striped_spins
+
+    for k, s0 in enumerate([random_spins(L, q, 5), striped_spins(L, q, 3)]):
+        _say(f"[parity-state] L={L} q={q} {model} start={k}")
+        t0 = 1000 + k
+        lat = swmc.Lattice(L, q, model, T=T, seed=21).set_spins(s0, t=t0)
+        ch = orc.Chain(L, q, model, T=T, seed=21, spins=s0, t=t0)
+        for _ in range(3):
+            lat.sweep(1, verify=True)
+            ch.sweep(1)
+            assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+            assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+        lat.close()
+
+
+def test_many_sweeps_batch_call(swmc, orc):
+    # 40 sweeps enqueued by one call; compare the end state and last labels.
+    L, q, T = 160, 2, TC2
+    _say("[parity-many] L=160 40 sweeps")
+    lat = swmc.Lattice(L, q, "potts", T=T, seed=99)
+    ch = orc.Chain(L, q, "potts", T=T, seed=99)
+    lat.sweep(40, verify=True)
+    ch.sweep(40)
+    assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+    assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+    assert lat.measure()["t"] == 40
+
+
+@pytest.mark.parametrize("q,model,T", [(2, "potts", TC2), (3, "potts", TC3), (6, "clock", 0.9)])
+def test_measurements(swmc, orc, q, model, T):
+    L, therm, nmeas = 48, 20, 300
+    _say(f"[measure] q={q} {model}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=31)
+    lat.sweep(therm)
+    lat.sweep(nmeas, measure=True)
+    ob = lat.measure()
+    e, m2, s_final = orc.run(L, q, model, T, 1.0, 31, therm, nmeas)
+    assert np.array_equal(lat.spins(), s_final)
+    ch = orc.Chain(L, q, model, T=T, seed=31, spins=s_final)
+    h, p = ch.counts()
+    assert np.array_equal(ob["hist"], h) and np.array_equal(ob["pair_hist"], p)
+    e_now, m2_now = ch.observables()
+    rel = lambda a, b: abs(a - b) <= 1e-12 * max(1.0, abs(b))
+    assert rel(ob["e"], e_now) and rel(ob["m2"], m2_now)
+    assert ob["samples"] == nmeas
+    assert rel(ob["mean_e"], e.mean()) and rel(ob["mean_m2"], m2.mean())
+    assert rel(ob["mean_m4"], (m2 * m2).mean())
+    U = (m2 * m2).mean() / m2.mean() ** 2
+    assert rel(ob["binder_u"], U)
+
+
+@pytest.mark.parametrize("model,q,T,nsw", [("potts", 2, TC2, 3), ("clock", 6, 0.9, 2)])
+def test_full_size_L4096(swmc, orc, model, q, T, nsw):
+    # The benchmark lattice at full size: whole-state comparison after a few
+    # sweeps (the oracle needs about a second per sweep here).
+    L = 4096
+    _say(f"[full] L=4096 {model} q={q}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=2)
+    ch = orc.Chain(L, q, model, T=T, seed=2)
+    for s in range(nsw):
+        lat.sweep(1, verify=True)
+        ch.sweep(1)
+        assert np.array_equal(lat.labels().reshape(-1), ch.labels), f"labels differ at sweep {s}"
+        assert np.array_equal(lat.spins().reshape(-1), ch.spins), f"spins differ at sweep {s}"
+    lat.close()
+
+
+def test_invalid_arguments_raise(swmc):
+    with pytest.raises(swmc.SwError):
+        swmc.Lattice(1, 2, "potts", T=1.0)
+    with pytest.raises(swmc.SwError):
+        swmc.Lattice(16, 33, "potts", T=1.0)
+    lat = swmc.Lattice(16, 3, "potts", T=1.0)
+    with pytest.raises(swmc.SwError):
+        lat.set_spins(np.full((16, 16), 3, np.int8))
+    with pytest.raises(swmc.SwError):
+        lat.labels()  # no SW_VERIFY sweep yet
+    with pytest.raises(swmc.SwError):
+        lat.sweep(-1)
