@@ -31,15 +31,15 @@ def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile
     k_bond_local: spins read once (1 B/site) plus the halo column and row of
       every tile (L*L*(1/tile_w + 1/tile_h) B), bonds written (2 bits/site =
       0.25 B/site), labels written (4 B/site).
-    k_border_merge: per tile-border site, one bond word bit-read (counted as
-      1/8 B) and the two label words of its endpoints read (8 B).
+    k_border_merge, k_flatten: per tile-border site, one bond bit read
+      (counted as 1/8 B) and the two label words of its endpoints (8 B).
     k_flip: labels read (4 B/site), spins written (1 B/site); the clock model
       also reads the old spin (1 B/site).
     """
     N = float(L) * L
     if kernel == "k_bond_local":
         return N * (1.0 + 1.0 / tile_w + 1.0 / tile_h + 0.25 + 4.0)
-    if kernel == "k_border_merge":
+    if kernel in ("k_border_merge", "k_flatten"):
         border = L * (-(-L // tile_w)) + L * (-(-L // tile_h))
         return border * (0.125 + 8.0)
     if kernel == "k_flip":
@@ -108,7 +108,7 @@ def main() -> int:
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     dom_bytes = alg_bytes_per_launch(dom, cfg.L, cfg.model)
     achieved = dom_bytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-    sweep_bytes = sum(alg_bytes_per_launch(k, cfg.L, cfg.model) for k in ("k_bond_local", "k_border_merge", "k_flip"))
+    sweep_bytes = sum(alg_bytes_per_launch(k, cfg.L, cfg.model) for k in ("k_bond_local", "k_border_merge", "k_flatten", "k_flip"))
     sweep_gbps = sweep_bytes / (ms * 1e-3 / args.steps) / 1e9
 
     paper = PAPER_NS_PER_UPDATE.get(cfg.name)

@@ -34,7 +34,7 @@ constexpr int kRowWords = 64;    // int64 per count row: hist[32], pair_hist[32]
 // Device control block at the start of the arena.
 struct Control {
     uint64_t t;       // sweep index of the current state
-    uint32_t done;    // finished-workgroup counter of the flip kernel
+    uint32_t mirror;  // clock model: mirror index of the sweep in progress
     uint32_t pad[13];
 };
 
@@ -56,10 +56,11 @@ struct SweepArgs {
 hipError_t launch_init(const SweepArgs& a, hipStream_t s);
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s);
 hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
+hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s);
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s);
 
-enum KernelId { kKBondLocal = 0, kKBorderMerge = 1, kKFlip = 2, kKCounts = 3, kNumKernels = 4 };
+enum KernelId { kKBondLocal = 0, kKBorderMerge = 1, kKFlatten = 2, kKFlip = 3, kKCounts = 4, kNumKernels = 5 };
 extern const char* const kKernelNames[kNumKernels];
 
 }  // namespace swmc

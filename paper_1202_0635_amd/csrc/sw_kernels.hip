@@ -1,6 +1,7 @@
 // HIP kernels of the Swendsen-Wang sweep for gfx950 (wave64, LDS union-find).
 //
-// One sweep = k_bond_local -> k_border_merge -> k_flip (Sec. 2 steps (1)-(3);
+// One sweep = k_bond_local -> k_border_merge -> k_flatten -> k_flip (Sec. 2
+// steps (1)-(3);
 // the GPU organisation of Sec. 3 is replaced by a non-iterative union-find):
 //   k_bond_local   per 64 x kTileH tile: FK bonds from Philox draws, row runs by
 //                  wave ballots, vertical unions in an LDS forest, tile-local
@@ -10,14 +11,16 @@
 //   k_border_merge one thread per bond that leaves a tile or wraps around the
 //                  torus: lock-free union of the two global roots, the larger
 //                  index linked under the smaller by compare-and-swap.
-//   k_flip         each site follows its forest path to the root word and
-//                  takes the root's value (Potts) or reflection (clock).
+//   k_flatten      points every linked tile-local root straight at its root.
+//   k_flip         each site follows its (now at most three-step) path to the
+//                  root word and takes the root's value (Potts) or
+//                  reflection (clock).
 #include "sw_device.hpp"
 #include "sw_internal.hpp"
 
 namespace swmc {
 
-const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_border_merge", "k_flip", "k_counts"};
+const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_border_merge", "k_flatten", "k_flip", "k_counts"};
 
 namespace {
 
@@ -58,11 +61,24 @@ __device__ __forceinline__ uint32_t g_load(const uint32_t* p) {
     return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root of x in the global forest; *word receives the root word.
-__device__ __forceinline__ uint32_t g_find(const uint32_t* lab, uint32_t x, uint32_t* word) {
+__device__ __forceinline__ void g_store(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x in the global forest; *word receives the root word.  Path
+// halving: a visited non-root is pointed at its grandparent.  Only non-root
+// words are rewritten and only with an ancestor's index, so a concurrent
+// compare-and-swap (which targets root words) is never disturbed.
+__device__ __forceinline__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* word) {
     uint32_t w = g_load(&lab[x]);
     while (!(w & kRootFlag)) {
-        x = w;
+        const uint32_t w2 = g_load(&lab[w]);
+        if (w2 & kRootFlag) {
+            *word = w2;
+            return w;
+        }
+        g_store(&lab[x], w2);
+        x = w2;
         w = g_load(&lab[x]);
     }
     *word = w;
@@ -112,15 +128,16 @@ __global__ void __launch_bounds__(256) k_init(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Bonds + tile-local labeling.
+// Bonds + tile-local labeling.  Lane = column, wave = kTileH/4 consecutive
+// rows; each spin is loaded once (its right neighbour comes from the next
+// lane, its lower neighbour from the next row held in registers).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     constexpr int RPW = kTileH / kWaves;  // rows per wave
-    __shared__ uint32_t P[kTileH * kTileW];
+    __shared__ uint32_t P[kTileH * kTileW];  // tile forest; afterwards each wave's root list
     __shared__ uint64_t in_r[kTileH];
     __shared__ uint64_t in_d[kTileH];
     __shared__ uint32_t cut[32 * 32];
-    __shared__ uint32_t roots[kWaves][RPW * kTileW];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -135,33 +152,56 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     const uint64_t in_tile_r = (nvalid >= 64) ? (~0ull >> 1) : ((1ull << (nvalid - 1)) - 1ull);
     const uint64_t t = a.ctl->t;
     const uint32_t k0 = a.key0, k1 = a.key1;
+    const bool clock = a.model == 1;
 
-    // Cutoff slice of this sweep: Potts C[a][b]; clock C[m][a][b] for the mirror m.
-    const int m = (a.model == 1) ? mirror_of(t, q, k0, k1) : 0;
-    const uint32_t* src = a.table + static_cast<size_t>(m) * q * q;
-    for (int k = threadIdx.x; k < q * q; k += kBlock) cut[k] = src[k];
+    // Cutoffs of this sweep: Potts needs only the equal-spin cutoff; the clock
+    // model reads the q x q slice of its mirror m from LDS.
+    const uint32_t c_eq = a.table[0];
+    if (clock) {
+        const int m = mirror_of(t, q, k0, k1);
+        const uint32_t* src = a.table + static_cast<size_t>(m) * q * q;
+        for (int k = threadIdx.x; k < q * q; k += kBlock) cut[k] = src[k];
+        if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->mirror = static_cast<uint32_t>(m);
+    }
     __syncthreads();
 
-    // Phase 1: bonds of the wave's rows, in groups of four rows per draw.
+    const int ly_base = wave * RPW;
+    const int y_base = y0 + ly_base;
+    int sreg[RPW + 1];
+#pragma unroll
+    for (int r = 0; r <= RPW; ++r) {
+        const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
+        sreg[r] = (col_ok && yr <= L) ? a.spins[static_cast<size_t>(yr == L ? 0 : yr) * L + x] : 0;
+    }
+    const bool edge_lane = (lane == nvalid - 1);
+
+    // Phase 1: bonds of the wave's rows, four rows per draw.
+#pragma unroll
     for (int g = 0; g < RPW / 4; ++g) {
-        const int ly0 = wave * RPW + g * 4;
+        const int ly0 = ly_base + g * 4;
         const int yb = y0 + ly0;  // multiple of 4
         Words4 hi = {0, 0, 0, 0};
-        if (col_ok && yb < L)
-            hi = draw(static_cast<uint32_t>((yb >> 2) * L + x), t, kBondHi, k0, k1);
+        if (col_ok && yb < L) hi = draw(static_cast<uint32_t>((yb >> 2) * L + x), t, kBondHi, k0, k1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
+            const int r = g * 4 + k;
             const int ly = ly0 + k;
             const int y = yb + k;
             const bool ok = col_ok && (y < L);
+            const int s = sreg[r];
+            const int sd = sreg[r + 1];
+            int sr = __shfl_down(s, 1, 64);
+            if (ok && edge_lane) sr = a.spins[static_cast<size_t>(y) * L + xr];
             bool br = false, bd = false;
             if (ok) {
-                const int yd = (y + 1 == L) ? 0 : y + 1;
-                const int s = a.spins[static_cast<size_t>(y) * L + x];
-                const int sr = a.spins[static_cast<size_t>(y) * L + xr];
-                const int sd = a.spins[static_cast<size_t>(yd) * L + x];
-                const uint32_t cr = cut[s * q + sr];
-                const uint32_t cd = cut[s * q + sd];
+                uint32_t cr, cd;
+                if (clock) {
+                    cr = cut[s * q + sr];
+                    cd = cut[s * q + sd];
+                } else {
+                    cr = (s == sr) ? c_eq : 0u;
+                    cd = (s == sd) ? c_eq : 0u;
+                }
                 const uint32_t w = (k == 0) ? hi.w0 : (k == 1) ? hi.w1 : (k == 2) ? hi.w2 : hi.w3;
                 const uint32_t ur = w >> 16, ud = w & 0xFFFFu;
                 br = ur < (cr >> 16);
@@ -169,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
                 const bool tie_r = (ur == (cr >> 16)) && (cr & 0xFFFFu);
                 const bool tie_d = (ud == (cd >> 16)) && (cd & 0xFFFFu);
                 if (tie_r || tie_d) {
-                    // low halves of the two uniforms, drawn only when needed
+                    // low halves of the two uniforms, drawn only when the high halves tie
                     const uint32_t lo = draw(static_cast<uint32_t>(static_cast<size_t>(y) * L + x), t, kBondLo, k0, k1).w0;
                     br = br || (tie_r && (lo >> 16) < (cr & 0xFFFFu));
                     bd = bd || (tie_d && (lo & 0xFFFFu) < (cd & 0xFFFFu));
@@ -198,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     // Phase 2: vertical unions inside the tile.  A bond is skipped when the
     // lane to its left carries a vertical bond between the same two runs.
     for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
+        const int ly = ly_base + r;
         if (ly + 1 >= kTileH) break;
         const uint64_t d = in_d[ly];
         if (!((d >> lane) & 1ull)) continue;
@@ -209,105 +249,175 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     }
     __syncthreads();
 
-    // Phase 3: tile-local roots -> global label forest.
-    uint32_t nroots = 0;
+    // Phase 3: tile-local roots.
+    uint32_t rootreg[RPW];
+#pragma unroll
     for (int r = 0; r < RPW; ++r) {
-        const int ly = wave * RPW + r;
-        const int y = y0 + ly;
+        const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
+        rootreg[r] = (col_ok && y_base + r < L) ? lds_find(P, self) : self;
+    }
+    __syncthreads();
+    uint32_t* list = P + ly_base * kTileW;  // this wave's slice of P holds its root list
+    uint32_t nroots = 0;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int y = y_base + r;
         const bool ok = col_ok && (y < L);
-        const uint32_t self = static_cast<uint32_t>(ly * kTileW + lane);
-        const uint32_t root = ok ? lds_find(P, self) : self;
+        const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
+        const uint32_t root = rootreg[r];
         const bool is_root = ok && (root == self);
-        if (ok && !is_root) {
-            const uint32_t g = static_cast<uint32_t>((y0 + static_cast<int>(root >> 6)) * L + x0 + static_cast<int>(root & 63));
-            a.labels[static_cast<size_t>(y) * L + x] = g;
-        }
+        if (ok && !is_root)
+            a.labels[static_cast<size_t>(y) * L + x] =
+                static_cast<uint32_t>((y0 + static_cast<int>(root >> 6)) * L + x0 + static_cast<int>(root & 63));
         const uint64_t rm = __ballot(is_root);
-        if (is_root) {
-            const uint32_t pos = nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)));
-            roots[wave][pos] = static_cast<uint32_t>(y * L + x);
-        }
+        if (is_root) list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] =
+            static_cast<uint32_t>(y * L + x);
         nroots += static_cast<uint32_t>(__popcll(rm));
     }
     __syncthreads();
-    // Every tile-local root draws its cluster's value (Sec. 3: a new value is
-    // assigned to every label; here only to labels that are roots).
+    // Every tile-local root draws its cluster's value (Sec. 3 assigns a new
+    // value to every label index; here only roots draw, one lane per root).
     for (uint32_t j = lane; j < nroots; j += 64) {
-        const uint32_t i = roots[wave][j];
+        const uint32_t i = list[j];
         const uint32_t w = draw(i, t, kCluster, k0, k1).w0;
-        const uint32_t v = (a.model == 0) ? qmap(w, static_cast<uint32_t>(q)) : (w >> 31);
+        const uint32_t v = clock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
         a.labels[i] = kRootFlag | v;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Union across tile borders and the periodic wrap.
+// Bonds that leave a tile (or wrap around the torus).  Thread g < nv: right
+// edge of tile column g / L, row g % L; otherwise bottom edge of a tile row.
+// The bond is skipped when the neighbouring bond along the same border joins
+// the same two tile-local sets (both its ends are tile-internal neighbours).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
+struct BorderBond {
+    bool active;
+    uint32_t i, j;
+};
+
+__device__ __forceinline__ BorderBond border_bond(const SweepArgs& a, size_t gid) {
     const int L = a.L;
     const size_t nv = static_cast<size_t>(a.tiles_x) * L;
     const size_t nh = static_cast<size_t>(a.tiles_y) * L;
-    const size_t gid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    BorderBond b{false, 0u, 0u};
     if (gid < nv) {
-        // right edge of tile column tx, row y
         const int tx = static_cast<int>(gid / L);
         const int y = static_cast<int>(gid % L);
         const int xe = min((tx + 1) * kTileW, L) - 1;
         const int xr = (xe + 1 == L) ? 0 : xe + 1;
-        if (!bond_bit(a.bond_r, a.w64, xe, y)) return;
-        // redundant if row y-1 of the same tile row already joins the same two sets
+        if (!bond_bit(a.bond_r, a.w64, xe, y)) return b;
         if ((y % kTileH) != 0 && bond_bit(a.bond_r, a.w64, xe, y - 1) && bond_bit(a.bond_d, a.w64, xe, y - 1) &&
             bond_bit(a.bond_d, a.w64, xr, y - 1))
-            return;
-        g_union(a.labels, static_cast<uint32_t>(y * L + xe), static_cast<uint32_t>(y * L + xr));
+            return b;
+        b = {true, static_cast<uint32_t>(y * L + xe), static_cast<uint32_t>(y * L + xr)};
     } else if (gid < nv + nh) {
         const size_t h = gid - nv;
         const int ty = static_cast<int>(h / L);
         const int x = static_cast<int>(h % L);
         const int ye = min((ty + 1) * kTileH, L) - 1;
         const int yd = (ye + 1 == L) ? 0 : ye + 1;
-        if (!bond_bit(a.bond_d, a.w64, x, ye)) return;
+        if (!bond_bit(a.bond_d, a.w64, x, ye)) return b;
         if ((x % kTileW) != 0 && bond_bit(a.bond_d, a.w64, x - 1, ye) && bond_bit(a.bond_r, a.w64, x - 1, ye) &&
             bond_bit(a.bond_r, a.w64, x - 1, yd))
-            return;
-        g_union(a.labels, static_cast<uint32_t>(ye * L + x), static_cast<uint32_t>(yd * L + x));
+            return b;
+        b = {true, static_cast<uint32_t>(ye * L + x), static_cast<uint32_t>(yd * L + x)};
     }
+    return b;
+}
+
+__global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
+    const BorderBond b = border_bond(a, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+    if (b.active) g_union(a.labels, b.i, b.j);
+}
+
+// After the merge: every linked tile-local root at the end of a border bond
+// is pointed straight at its cluster root, so that any site reaches the root
+// word in at most three loads (site -> tile-local root -> root).
+__device__ __forceinline__ void flatten_from(uint32_t* lab, uint32_t e) {
+    uint32_t w = lab[e];
+    uint32_t r = e;
+    if (!(w & kRootFlag)) {
+        r = w;
+        w = lab[r];
+    }
+    if (w & kRootFlag) return;  // the tile-local root is still a cluster root
+    uint32_t x = w;             // walk to the root, halving the path on the way
+    uint32_t wx = lab[x];
+    while (!(wx & kRootFlag)) {
+        const uint32_t w2 = lab[wx];
+        if (w2 & kRootFlag) {
+            x = wx;
+            break;
+        }
+        lab[x] = w2;
+        x = w2;
+        wx = lab[x];
+    }
+    lab[r] = x;
+}
+
+__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) {
+    // Every kernel that reads the sweep index has finished (stream order); the
+    // flip only needs the mirror recorded by k_bond_local.
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->t += 1;
+    const BorderBond b = border_bond(a, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+    if (!b.active) return;
+    flatten_from(a.labels, b.i);
+    flatten_from(a.labels, b.j);
 }
 
 // ---------------------------------------------------------------------------
-// Cluster flip; the last workgroup advances the sweep index.
+// Cluster flip, four sites per thread.
 // ---------------------------------------------------------------------------
 template <bool kVerify>
 __global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
     const size_t N = static_cast<size_t>(a.L) * a.L;
-    const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t t = a.ctl->t;
-    if (i < N) {
-        uint32_t x = static_cast<uint32_t>(i);
-        uint32_t w = a.labels[i];
-        while (!(w & kRootFlag)) {
-            x = w;
-            w = a.labels[x];
+    const size_t base = (static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
+    const bool clock = a.model == 1;
+    if (base < N) {
+        const int n = (N - base >= 4) ? 4 : static_cast<int>(N - base);
+        uint32_t x[4], w[4];
+        if (n == 4) {
+            const uint4 v = *reinterpret_cast<const uint4*>(a.labels + base);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+            for (int k = 0; k < 4; ++k) w[k] = (k < n) ? a.labels[base + k] : kRootFlag;
         }
-        const uint32_t v = w & 0xFFu;
-        if (a.model == 0) {
-            a.spins[i] = static_cast<int8_t>(v);
-        } else if (v) {
-            const int m = mirror_of(t, a.q, a.key0, a.key1);
-            int s = m - a.spins[i];
-            if (s < 0) s += a.q;
-            a.spins[i] = static_cast<int8_t>(s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = static_cast<uint32_t>(base + k);
+        // follow the four paths together (independent loads in flight)
+        while (!((w[0] & w[1] & w[2] & w[3]) & kRootFlag)) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (!(w[k] & kRootFlag)) {
+                    x[k] = w[k];
+                    w[k] = a.labels[x[k]];
+                }
         }
-        if (kVerify) a.canon[i] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t nblocks = gridDim.x;
-        const uint32_t prev = atomicAdd(&a.ctl->done, 1u);
-        if (prev == nblocks - 1) {
-            a.ctl->done = 0;
-            a.ctl->t = t + 1;
+        uint32_t out[4];
+        if (!clock) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[k] = w[k] & 0xFFu;
+        } else {
+            const int m = static_cast<int>(a.ctl->mirror);
+            for (int k = 0; k < 4; ++k) {
+                int s = (k < n) ? a.spins[base + k] : 0;
+                if (w[k] & 1u) {
+                    s = m - s;
+                    if (s < 0) s += a.q;
+                }
+                out[k] = static_cast<uint32_t>(s);
+            }
+        }
+        if (n == 4) {
+            *reinterpret_cast<uint32_t*>(a.spins + base) = out[0] | (out[1] << 8) | (out[2] << 16) | (out[3] << 24);
+            if (kVerify) *reinterpret_cast<uint4*>(a.canon + base) = make_uint4(x[0], x[1], x[2], x[3]);
+        } else {
+            for (int k = 0; k < n; ++k) {
+                a.spins[base + k] = static_cast<int8_t>(out[k]);
+                if (kVerify) a.canon[base + k] = x[k];
+            }
         }
     }
 }
@@ -359,9 +469,15 @@ hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_flatten(const SweepArgs& a, hipStream_t s) {
+    const size_t n = (static_cast<size_t>(a.tiles_x) + a.tiles_y) * a.L;
+    hipLaunchKernelGGL(k_flatten, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
     const size_t N = static_cast<size_t>(a.L) * a.L;
-    const dim3 grid(static_cast<unsigned>((N + 255) / 256));
+    const dim3 grid(static_cast<unsigned>((N + 1023) / 1024));
     if (verify)
         hipLaunchKernelGGL(k_flip<true>, grid, dim3(256), 0, s, a);
     else

@@ -174,8 +174,8 @@ struct sw_ctx {
     // per-kernel timing
     std::vector<hipEvent_t> free_events;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-    int64_t prof_launches[kNumKernels] = {0, 0, 0, 0};
-    double prof_ms[kNumKernels] = {0, 0, 0, 0};
+    int64_t prof_launches[kNumKernels] = {};
+    double prof_ms[kNumKernels] = {};
 };
 
 namespace {
@@ -351,6 +351,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(c->args, c->stream); });
         if (st) return st;
         st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(c->args, c->stream); });
+        if (st) return st;
+        st = timed(c, profile, kKFlatten, [&] { return launch_flatten(c->args, c->stream); });
         if (st) return st;
         st = timed(c, profile, kKFlip, [&] { return launch_flip(c->args, verify, c->stream); });
         if (st) return st;
