@@ -39,9 +39,13 @@ def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile
     N = float(L) * L
     if kernel == "k_bond_local":
         return N * (1.0 + 1.0 / tile_w + 1.0 / tile_h + 0.25 + 4.0)
-    if kernel in ("k_border_merge", "k_flatten"):
-        border = L * (-(-L // tile_w)) + L * (-(-L // tile_h))
-        return border * (0.125 + 8.0)
+    if kernel in ("k_block_merge", "k_border_merge", "k_flatten"):
+        tiles = (-(-L // tile_w)) + (-(-L // tile_h))
+        if kernel == "k_border_merge":   # block borders only (every 4th tile border, and the wrap)
+            tiles = (-(-L // (4 * tile_w))) + (-(-L // (4 * tile_h)))
+        elif kernel == "k_block_merge":
+            tiles -= (-(-L // (4 * tile_w))) + (-(-L // (4 * tile_h)))
+        return L * tiles * (0.125 + 8.0)
     if kernel == "k_flip":
         return N * (4.0 + 1.0 + (1.0 if model == "clock" else 0.0))
     if kernel == "k_counts":
@@ -108,7 +112,7 @@ def main() -> int:
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     dom_bytes = alg_bytes_per_launch(dom, cfg.L, cfg.model)
     achieved = dom_bytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-    sweep_bytes = sum(alg_bytes_per_launch(k, cfg.L, cfg.model) for k in ("k_bond_local", "k_border_merge", "k_flatten", "k_flip"))
+    sweep_bytes = sum(alg_bytes_per_launch(k, cfg.L, cfg.model) for k in ("k_bond_local", "k_block_merge", "k_border_merge", "k_flatten", "k_flip"))
     sweep_gbps = sweep_bytes / (ms * 1e-3 / args.steps) / 1e9
 
     paper = PAPER_NS_PER_UPDATE.get(cfg.name)

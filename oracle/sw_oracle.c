@@ -13,12 +13,14 @@
  *       first), counter (c0, t mod 2^32, purpose, t >> 32).  The paper used a
  *       linear congruential generator (Sec. 3, last paragraph); a counter-based
  *       generator makes every draw a pure function of (seed, site, sweep).
- *   R2  Bond uniforms are 32-bit: u = (hi << 16) | lo.  The high halves come
- *       from one draw per column and group of four rows (purpose 0,
- *       c0 = (y div 4)*L + x; word k serves row 4*(y div 4)+k; its upper 16
- *       bits belong to the right bond, its lower 16 bits to the down bond).
- *       The low halves come from a draw per site (purpose 1, c0 = i; word 0,
- *       upper 16 bits right bond, lower 16 bits down bond).
+ *   R2  Bond uniforms are 32-bit: u = (hi << 24) | lo.  The high bytes come
+ *       from one draw per column and group of eight rows (purpose 0,
+ *       c0 = (y div 8)*L + x): word k serves rows 8*(y div 8) + 2k and
+ *       8*(y div 8) + 2k + 1; its bytes, most significant first, are the right
+ *       and the down bond of the first of these rows, then the right and the
+ *       down bond of the second.  The low 24 bits come from a draw per site
+ *       (purpose 1, c0 = i): word 0 for the right bond, word 1 for the down
+ *       bond.
  *   R3  A bond is active iff u < C(s_i, s_j), with the cutoff
  *       C = floor(2^32 * p) from a host FP64 table, p = 1 - exp(-x) evaluated
  *       as -expm1(-x), clamped to 2^32-1.  Potts: x = J/T for equal spins and
@@ -208,11 +210,14 @@ void or_bonds(int L, int q, int model, const uint32_t* table, uint64_t seed, uin
             int64_t j_right = (int64_t)y * L + (x + 1) % L;
             int64_t j_down = (int64_t)((y + 1) % L) * L + x;
             uint32_t w_hi[4], w_lo[4];
-            or_draw(seed, (uint32_t)((int64_t)(y / 4) * L + x), t, OR_P_BOND_HI, w_hi);
+            or_draw(seed, (uint32_t)((int64_t)(y / 8) * L + x), t, OR_P_BOND_HI, w_hi);
             or_draw(seed, (uint32_t)i, t, OR_P_BOND_LO, w_lo);
-            uint32_t hi = w_hi[y % 4];
-            uint32_t u_right = (hi & 0xFFFF0000u) | (w_lo[0] >> 16);
-            uint32_t u_down = (hi << 16) | (w_lo[0] & 0xFFFFu);
+            uint32_t word = w_hi[(y % 8) / 2];
+            int shift = (y % 2 == 0) ? 16 : 0; /* this row's two bytes */
+            uint32_t hi_right = (word >> (shift + 8)) & 0xFFu;
+            uint32_t hi_down = (word >> shift) & 0xFFu;
+            uint32_t u_right = (hi_right << 24) | (w_lo[0] & 0x00FFFFFFu);
+            uint32_t u_down = (hi_down << 24) | (w_lo[1] & 0x00FFFFFFu);
             int a = spins[i];
             bond_r[i] = (uint8_t)(u_right < C[a * q + spins[j_right]]);
             bond_d[i] = (uint8_t)(u_down < C[a * q + spins[j_down]]);

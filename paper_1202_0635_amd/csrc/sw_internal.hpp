@@ -14,6 +14,8 @@ constexpr int kTileW = 64;
 constexpr int kTileH = 64;
 constexpr int kWaves = 4;
 constexpr int kBlock = kWaves * 64;
+// Tiles per side of the blocks whose inner borders the first merge level joins.
+constexpr int kMergeTiles = 4;
 
 // Random-number purposes (third counter word of a Philox draw).
 constexpr uint32_t kBondHi = 0;
@@ -55,12 +57,13 @@ struct SweepArgs {
 // Launch wrappers (defined in sw_kernels.hip).
 hipError_t launch_init(const SweepArgs& a, hipStream_t s);
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s);
+hipError_t launch_block_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s);
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s);
 
-enum KernelId { kKBondLocal = 0, kKBorderMerge = 1, kKFlatten = 2, kKFlip = 3, kKCounts = 4, kNumKernels = 5 };
+enum KernelId { kKBondLocal = 0, kKBlockMerge = 1, kKBorderMerge = 2, kKFlatten = 3, kKFlip = 4, kKCounts = 5, kNumKernels = 6 };
 extern const char* const kKernelNames[kNumKernels];
 
 }  // namespace swmc

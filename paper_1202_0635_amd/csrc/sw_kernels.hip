@@ -20,7 +20,7 @@
 
 namespace swmc {
 
-const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_border_merge", "k_flatten", "k_flip", "k_counts"};
+const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge", "k_border_merge", "k_flatten", "k_flip", "k_counts"};
 
 namespace {
 
@@ -28,11 +28,21 @@ __device__ __forceinline__ uint32_t lds_load(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Root of x in the tile forest (parents always have smaller indices).
+__device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of x in the tile forest (parents always have smaller indices), with
+// path halving: a visited node is pointed at its grandparent.  A halving store
+// may overwrite a concurrent lowering of that node; the union that lowered it
+// continues with the node's previous parent, so no connection is lost.
 __device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x) {
     uint32_t p = lds_load(&P[x]);
     while (p != x) {
-        x = p;
+        const uint32_t gp = lds_load(&P[p]);
+        if (gp == p) return p;
+        lds_store(&P[x], gp);
+        x = gp;
         p = lds_load(&P[x]);
     }
     return x;
@@ -85,10 +95,35 @@ __device__ __forceinline__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* 
     return x;
 }
 
+// Root of x through ordinary (cached) loads, halving the path on the way.
+// Every word written before this kernel is visible; a word linked meanwhile
+// may be seen stale, which at worst makes the following compare-and-swap
+// fail.  A word read as a non-root can no longer be a root, so the halving
+// stores never touch the root words the compare-and-swap works on.
+__device__ __forceinline__ uint32_t c_find(uint32_t* lab, uint32_t x, uint32_t* word) {
+    uint32_t w = lab[x];
+    while (!(w & kRootFlag)) {
+        const uint32_t w2 = lab[w];
+        if (w2 & kRootFlag) {
+            *word = w2;
+            return w;
+        }
+        lab[x] = w2;
+        x = w2;
+        w = lab[x];
+    }
+    *word = w;
+    return x;
+}
+
+// Join the clusters of sites a and b: the larger root is linked under the
+// smaller one by compare-and-swap on its root word.  The first attempt walks
+// the forest through the caches; after a failed swap the walk uses coherent
+// loads (and halves the paths it visits).
 __device__ void g_union(uint32_t* lab, uint32_t a, uint32_t b) {
     uint32_t wa, wb;
-    a = g_find(lab, a, &wa);
-    b = g_find(lab, b, &wb);
+    a = c_find(lab, a, &wa);
+    b = c_find(lab, b, &wb);
     while (a != b) {
         if (a > b) {
             uint32_t tmp = a;
@@ -98,7 +133,6 @@ __device__ void g_union(uint32_t* lab, uint32_t a, uint32_t b) {
             wa = wb;
             wb = tmp;
         }
-        // link root b under the smaller root a, if b is still a root
         uint32_t expected = wb;
         if (__hip_atomic_compare_exchange_strong(&lab[b], &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
@@ -128,16 +162,26 @@ __global__ void __launch_bounds__(256) k_init(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Bonds + tile-local labeling.  Lane = column, wave = kTileH/4 consecutive
-// rows; each spin is loaded once (its right neighbour comes from the next
-// lane, its lower neighbour from the next row held in registers).
+// Bonds + tile-local labeling.  Lane = column; each wave owns kTileH/4
+// consecutive rows.  Each spin is loaded once: its right neighbour comes from
+// the next lane, its lower neighbour from the next row held in registers.
+// The 32-bit bond uniforms are u = (hi << 24) | lo: one draw gives the high
+// bytes of eight rows of a column; the low 24 bits only matter when a high
+// byte equals the cutoff's high byte (probability 2^-8), so those ties are
+// collected in a tile-wide list and resolved with one draw per tied site.
 // ---------------------------------------------------------------------------
+template <int kModel>
 __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
+    constexpr bool kClock = kModel == 1;
     constexpr int RPW = kTileH / kWaves;  // rows per wave
-    __shared__ uint32_t P[kTileH * kTileW];  // tile forest; afterwards each wave's root list
-    __shared__ uint64_t in_r[kTileH];
-    __shared__ uint64_t in_d[kTileH];
-    __shared__ uint32_t cut[32 * 32];
+    static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
+    __shared__ uint32_t P[kTileH * kTileW];  // tie list, then the tile forest, then root lists
+    __shared__ uint64_t raw_r[kTileH];       // right-bond masks of the tile's rows
+    __shared__ uint64_t raw_d[kTileH];       // down-bond masks
+    __shared__ uint32_t cut[kClock ? 32 * 32 : 1];
+    __shared__ int halo[kTileH];             // spins of the column right of the tile
+    __shared__ uint32_t slot[kWaves][kTileW];  // per-run minimum of the labelling pass
+    __shared__ uint32_t ntie;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -146,22 +190,26 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     const int x0 = tx * kTileW, y0 = ty * kTileH;
     const int x = x0 + lane;
     const bool col_ok = x < L;
-    const int xr = (x + 1 == L) ? 0 : x + 1;
     const int nvalid = min(kTileW, L - x0);
     // lanes whose right bond stays inside the tile (not the last column, no wrap)
     const uint64_t in_tile_r = (nvalid >= 64) ? (~0ull >> 1) : ((1ull << (nvalid - 1)) - 1ull);
     const uint64_t t = a.ctl->t;
     const uint32_t k0 = a.key0, k1 = a.key1;
-    const bool clock = a.model == 1;
 
     // Cutoffs of this sweep: Potts needs only the equal-spin cutoff; the clock
     // model reads the q x q slice of its mirror m from LDS.
     const uint32_t c_eq = a.table[0];
-    if (clock) {
+    if (kClock) {
         const int m = mirror_of(t, q, k0, k1);
         const uint32_t* src = a.table + static_cast<size_t>(m) * q * q;
         for (int k = threadIdx.x; k < q * q; k += kBlock) cut[k] = src[k];
         if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->mirror = static_cast<uint32_t>(m);
+    }
+    if (threadIdx.x == 0) ntie = 0;
+    if (threadIdx.x < kTileH) {
+        const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
+        const int yh = y0 + static_cast<int>(threadIdx.x);
+        halo[threadIdx.x] = (yh < L) ? a.spins[static_cast<size_t>(yh) * L + xh] : 0;
     }
     __syncthreads();
 
@@ -175,86 +223,146 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     }
     const bool edge_lane = (lane == nvalid - 1);
 
-    // Phase 1: bonds of the wave's rows, four rows per draw.
+    // Phase 1: decisions on the high bytes; ties go to the list.
 #pragma unroll
-    for (int g = 0; g < RPW / 4; ++g) {
-        const int ly0 = ly_base + g * 4;
-        const int yb = y0 + ly0;  // multiple of 4
+    for (int g = 0; g < RPW / 8; ++g) {
+        const int ly0 = ly_base + g * 8;
+        const int yb = y0 + ly0;  // multiple of 8
         Words4 hi = {0, 0, 0, 0};
-        if (col_ok && yb < L) hi = draw(static_cast<uint32_t>((yb >> 2) * L + x), t, kBondHi, k0, k1);
+        if (col_ok && yb < L) hi = draw(static_cast<uint32_t>((yb >> 3) * L + x), t, kBondHi, k0, k1);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r = g * 4 + k;
+        for (int k = 0; k < 8; ++k) {
+            const int r = g * 8 + k;
             const int ly = ly0 + k;
-            const int y = yb + k;
-            const bool ok = col_ok && (y < L);
+            const bool ok = col_ok && (yb + k < L);
             const int s = sreg[r];
             const int sd = sreg[r + 1];
-            int sr = __shfl_down(s, 1, 64);
-            if (ok && edge_lane) sr = a.spins[static_cast<size_t>(y) * L + xr];
-            bool br = false, bd = false;
-            if (ok) {
-                uint32_t cr, cd;
-                if (clock) {
-                    cr = cut[s * q + sr];
-                    cd = cut[s * q + sd];
-                } else {
-                    cr = (s == sr) ? c_eq : 0u;
-                    cd = (s == sd) ? c_eq : 0u;
-                }
-                const uint32_t w = (k == 0) ? hi.w0 : (k == 1) ? hi.w1 : (k == 2) ? hi.w2 : hi.w3;
-                const uint32_t ur = w >> 16, ud = w & 0xFFFFu;
-                br = ur < (cr >> 16);
-                bd = ud < (cd >> 16);
-                const bool tie_r = (ur == (cr >> 16)) && (cr & 0xFFFFu);
-                const bool tie_d = (ud == (cd >> 16)) && (cd & 0xFFFFu);
-                if (tie_r || tie_d) {
-                    // low halves of the two uniforms, drawn only when the high halves tie
-                    const uint32_t lo = draw(static_cast<uint32_t>(static_cast<size_t>(y) * L + x), t, kBondLo, k0, k1).w0;
-                    br = br || (tie_r && (lo >> 16) < (cr & 0xFFFFu));
-                    bd = bd || (tie_d && (lo & 0xFFFFu) < (cd & 0xFFFFu));
-                }
+            const int sr_next = __shfl_down(s, 1, 64);
+            const int sr = edge_lane ? halo[ly] : sr_next;
+            const uint32_t word = (k < 2) ? hi.w0 : (k < 4) ? hi.w1 : (k < 6) ? hi.w2 : hi.w3;
+            const uint32_t hr = (k & 1) ? ((word >> 8) & 0xFFu) : (word >> 24);
+            const uint32_t hd = (k & 1) ? (word & 0xFFu) : ((word >> 16) & 0xFFu);
+            uint32_t cr, cd;
+            if (kClock) {
+                cr = cut[s * q + sr];
+                cd = cut[s * q + sd];
+            } else {
+                cr = (s == sr) ? c_eq : 0u;
+                cd = (s == sd) ? c_eq : 0u;
             }
+            const bool br = ok && (hr < (cr >> 24));
+            const bool bd = ok && (hd < (cd >> 24));
+            const bool tr = ok && (hr == (cr >> 24)) && (cr & 0xFFFFFFu);
+            const bool td = ok && (hd == (cd >> 24)) && (cd & 0xFFFFFFu);
             const uint64_t mr = __ballot(br);
             const uint64_t md = __ballot(bd);
-            if (lane == 0 && y < L) {
-                a.bond_r[static_cast<size_t>(y) * a.w64 + tx] = mr;
-                a.bond_d[static_cast<size_t>(y) * a.w64 + tx] = md;
-            }
-            const uint64_t ir = mr & in_tile_r;
-            const uint64_t id = (ly + 1 < kTileH && y + 1 < L) ? md : 0ull;
             if (lane == 0) {
-                in_r[ly] = ir;
-                in_d[ly] = id;
+                raw_r[ly] = mr;
+                raw_d[ly] = md;
             }
-            // run start: the highest lane j <= lane with no in-tile bond from j-1 to j
-            const uint64_t brk = ~(ir << 1);
-            const int start = 63 - __clzll(brk & (~0ull >> (63 - lane)));
-            P[ly * kTileW + lane] = static_cast<uint32_t>(ly * kTileW + start);
+            if (tr || td) {
+                const uint32_t pos = atomicAdd(&ntie, 1u);
+                P[pos] = static_cast<uint32_t>(ly * kTileW + lane) | (tr ? 1u << 12 : 0u) | (td ? 1u << 13 : 0u);
+            }
         }
     }
     __syncthreads();
 
-    // Phase 2: vertical unions inside the tile.  A bond is skipped when the
-    // lane to its left carries a vertical bond between the same two runs.
-    for (int r = 0; r < RPW; ++r) {
-        const int ly = ly_base + r;
-        if (ly + 1 >= kTileH) break;
-        const uint64_t d = in_d[ly];
-        if (!((d >> lane) & 1ull)) continue;
-        if (lane > 0 && ((d >> (lane - 1)) & 1ull) && ((in_r[ly] >> (lane - 1)) & 1ull) &&
-            ((in_r[ly + 1] >> (lane - 1)) & 1ull))
-            continue;
-        lds_union(P, static_cast<uint32_t>(ly * kTileW + lane), static_cast<uint32_t>((ly + 1) * kTileW + lane));
+    // Phase 1b: ties resolved by the low 24 bits of the per-site draw.
+    const uint32_t nt = ntie;
+    for (uint32_t j = threadIdx.x; j < nt; j += kBlock) {
+        const uint32_t e = P[j];
+        const int ly = static_cast<int>((e & 0xFFFu) >> 6), lx = static_cast<int>(e & 63u);
+        const int y = y0 + ly, xx = x0 + lx;
+        const size_t i = static_cast<size_t>(y) * L + xx;
+        const Words4 lo = draw(static_cast<uint32_t>(i), t, kBondLo, k0, k1);
+        const int s = a.spins[i];
+        if (e & (1u << 12)) {
+            const int sr = a.spins[static_cast<size_t>(y) * L + ((xx + 1 == L) ? 0 : xx + 1)];
+            const uint32_t c = kClock ? cut[s * q + sr] : c_eq;  // a Potts tie implies equal spins
+            if ((lo.w0 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_r[ly], 1ull << lx);
+        }
+        if (e & (1u << 13)) {
+            const int sd = a.spins[static_cast<size_t>((y + 1 == L) ? 0 : y + 1) * L + xx];
+            const uint32_t c = kClock ? cut[s * q + sd] : c_eq;
+            if ((lo.w1 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_d[ly], 1ull << lx);
+        }
     }
     __syncthreads();
 
-    // Phase 3: tile-local roots.
+    // Final bond masks to memory: one 64-bit word per row and direction.
+    if (threadIdx.x < 2 * kTileH) {
+        const int ly = threadIdx.x & (kTileH - 1);
+        const int y = y0 + ly;
+        if (y < L) {
+            if (threadIdx.x < kTileH)
+                a.bond_r[static_cast<size_t>(y) * a.w64 + tx] = raw_r[ly];
+            else
+                a.bond_d[static_cast<size_t>(y) * a.w64 + tx] = raw_d[ly];
+        }
+    }
+    // Phase 2: each wave labels its strip of rows in raster order, as the
+    // Hoshen-Kopelman scan does (Sec. 2): a run of the current row takes the
+    // smallest root among the sites above it that it is bonded to (or becomes
+    // a new root at its first site), and the other roots it touches are
+    // joined to that one.  P holds, for each site, its run's first site, and
+    // for a run's first site, the run's label.
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t run_start_rows = 0;
+    {
+        uint32_t* my_slot = slot[wave];
+        uint32_t lab_prev = kNone;
+        for (int r = 0; r < RPW; ++r) {
+            const int ly = ly_base + r;
+            const uint64_t ir = raw_r[ly] & in_tile_r;
+            const int start = 63 - __clzll(~(ir << 1) & (~0ull >> (63 - lane)));
+            if (start == lane) run_start_rows |= 1u << r;
+            const uint32_t node = static_cast<uint32_t>(ly * kTileW + start);
+            uint32_t cand = kNone;
+            if (r > 0 && y0 + ly < L && ((raw_d[ly - 1] >> lane) & 1ull)) cand = lds_find(P, lab_prev);
+            if (start == lane) my_slot[lane] = kNone;
+            __builtin_amdgcn_wave_barrier();
+            if (cand != kNone) atomicMin(&my_slot[start], cand);
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t m = my_slot[start];
+            const uint32_t lab = (m == kNone) ? node : m;
+            P[ly * kTileW + lane] = (start == lane) ? lab : node;
+            __builtin_amdgcn_wave_barrier();
+            if (cand != kNone && cand != m) lds_union(P, cand, m);
+            lab_prev = lab;
+        }
+    }
+    __syncthreads();
+
+    // Phase 2b: vertical bonds between the strips of consecutive waves.  A
+    // bond is skipped when the lane to its left carries a vertical bond
+    // between the same two runs.
+    if (wave + 1 < kWaves) {
+        const int ly = ly_base + RPW - 1;
+        const uint64_t d = (y0 + ly + 1 < L) ? raw_d[ly] : 0ull;
+        if (((d >> lane) & 1ull) &&
+            !(lane > 0 && ((d >> (lane - 1)) & 1ull) && ((raw_r[ly] >> (lane - 1)) & 1ull) &&
+              ((raw_r[ly + 1] >> (lane - 1)) & 1ull)))
+            lds_union(P, static_cast<uint32_t>(ly * kTileW + lane), static_cast<uint32_t>((ly + 1) * kTileW + lane));
+    }
+    __syncthreads();
+
+    // Phase 3: tile-local roots.  Run starts are pointed straight at their
+    // root, after which any site reaches its root in two loads.
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if ((run_start_rows >> r) & 1u) {
+            const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
+            const uint32_t root = lds_find(P, self);
+            lds_store(&P[self], root);
+        }
+    }
+    __syncthreads();
     uint32_t rootreg[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
-        rootreg[r] = (col_ok && y_base + r < L) ? lds_find(P, self) : self;
+        rootreg[r] = P[P[self]];
     }
     __syncthreads();
     uint32_t* list = P + ly_base * kTileW;  // this wave's slice of P holds its root list
@@ -270,8 +378,8 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
             a.labels[static_cast<size_t>(y) * L + x] =
                 static_cast<uint32_t>((y0 + static_cast<int>(root >> 6)) * L + x0 + static_cast<int>(root & 63));
         const uint64_t rm = __ballot(is_root);
-        if (is_root) list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] =
-            static_cast<uint32_t>(y * L + x);
+        if (is_root)
+            list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] = static_cast<uint32_t>(y * L + x);
         nroots += static_cast<uint32_t>(__popcll(rm));
     }
     __syncthreads();
@@ -280,7 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     for (uint32_t j = lane; j < nroots; j += 64) {
         const uint32_t i = list[j];
         const uint32_t w = draw(i, t, kCluster, k0, k1).w0;
-        const uint32_t v = clock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
+        const uint32_t v = kClock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
         a.labels[i] = kRootFlag | v;
     }
 }
@@ -296,38 +404,133 @@ struct BorderBond {
     uint32_t i, j;
 };
 
+// Right-edge bond of tile column tx in row y (wrapping to column 0 after the
+// last column).  Skipped when row y-1 of the same tile row already joins the
+// same two tile-local sets: both of its ends are tile-internal neighbours.
+__device__ __forceinline__ BorderBond vertical_border_bond(const SweepArgs& a, int tx, int y) {
+    const int L = a.L;
+    const int xe = min((tx + 1) * kTileW, L) - 1;
+    const int xr = (xe + 1 == L) ? 0 : xe + 1;
+    if (!bond_bit(a.bond_r, a.w64, xe, y)) return {false, 0u, 0u};
+    if ((y % kTileH) != 0 && bond_bit(a.bond_r, a.w64, xe, y - 1) && bond_bit(a.bond_d, a.w64, xe, y - 1) &&
+        bond_bit(a.bond_d, a.w64, xr, y - 1))
+        return {false, 0u, 0u};
+    return {true, static_cast<uint32_t>(y * L + xe), static_cast<uint32_t>(y * L + xr)};
+}
+
+// Bottom-edge bond of tile row ty in column x (wrapping to row 0).
+__device__ __forceinline__ BorderBond horizontal_border_bond(const SweepArgs& a, int ty, int x) {
+    const int L = a.L;
+    const int ye = min((ty + 1) * kTileH, L) - 1;
+    const int yd = (ye + 1 == L) ? 0 : ye + 1;
+    if (!bond_bit(a.bond_d, a.w64, x, ye)) return {false, 0u, 0u};
+    if ((x % kTileW) != 0 && bond_bit(a.bond_d, a.w64, x - 1, ye) && bond_bit(a.bond_r, a.w64, x - 1, ye) &&
+        bond_bit(a.bond_r, a.w64, x - 1, yd))
+        return {false, 0u, 0u};
+    return {true, static_cast<uint32_t>(ye * L + x), static_cast<uint32_t>(yd * L + x)};
+}
+
+// Thread g of a launch over every tile border: g < tiles_x*L is a vertical
+// border position, the rest horizontal.
 __device__ __forceinline__ BorderBond border_bond(const SweepArgs& a, size_t gid) {
     const int L = a.L;
     const size_t nv = static_cast<size_t>(a.tiles_x) * L;
     const size_t nh = static_cast<size_t>(a.tiles_y) * L;
-    BorderBond b{false, 0u, 0u};
-    if (gid < nv) {
-        const int tx = static_cast<int>(gid / L);
-        const int y = static_cast<int>(gid % L);
-        const int xe = min((tx + 1) * kTileW, L) - 1;
-        const int xr = (xe + 1 == L) ? 0 : xe + 1;
-        if (!bond_bit(a.bond_r, a.w64, xe, y)) return b;
-        if ((y % kTileH) != 0 && bond_bit(a.bond_r, a.w64, xe, y - 1) && bond_bit(a.bond_d, a.w64, xe, y - 1) &&
-            bond_bit(a.bond_d, a.w64, xr, y - 1))
-            return b;
-        b = {true, static_cast<uint32_t>(y * L + xe), static_cast<uint32_t>(y * L + xr)};
-    } else if (gid < nv + nh) {
+    if (gid < nv) return vertical_border_bond(a, static_cast<int>(gid / L), static_cast<int>(gid % L));
+    if (gid < nv + nh) {
         const size_t h = gid - nv;
-        const int ty = static_cast<int>(h / L);
-        const int x = static_cast<int>(h % L);
-        const int ye = min((ty + 1) * kTileH, L) - 1;
-        const int yd = (ye + 1 == L) ? 0 : ye + 1;
-        if (!bond_bit(a.bond_d, a.w64, x, ye)) return b;
-        if ((x % kTileW) != 0 && bond_bit(a.bond_d, a.w64, x - 1, ye) && bond_bit(a.bond_r, a.w64, x - 1, ye) &&
-            bond_bit(a.bond_r, a.w64, x - 1, yd))
-            return b;
-        b = {true, static_cast<uint32_t>(ye * L + x), static_cast<uint32_t>(yd * L + x)};
+        return horizontal_border_bond(a, static_cast<int>(h / L), static_cast<int>(h % L));
     }
-    return b;
+    return {false, 0u, 0u};
 }
 
+// ---------------------------------------------------------------------------
+// Merge, level 1: one workgroup per block of kMergeTiles x kMergeTiles tiles
+// joins the block's internal tile borders.  The forest nodes it visits (the
+// block's sites and tile-local roots) belong to no other workgroup during
+// this kernel, so workgroup-scope atomics and cached loads suffice.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wg_load(const uint32_t* p) {
+    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t wg_find(uint32_t* lab, uint32_t x, uint32_t* word) {
+    uint32_t w = wg_load(&lab[x]);
+    while (!(w & kRootFlag)) {
+        const uint32_t w2 = wg_load(&lab[w]);
+        if (w2 & kRootFlag) {
+            *word = w2;
+            return w;
+        }
+        __hip_atomic_store(&lab[x], w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = w2;
+        w = wg_load(&lab[x]);
+    }
+    *word = w;
+    return x;
+}
+
+__device__ void wg_union(uint32_t* lab, uint32_t a, uint32_t b) {
+    uint32_t wa, wb;
+    a = wg_find(lab, a, &wa);
+    b = wg_find(lab, b, &wb);
+    while (a != b) {
+        if (a > b) {
+            uint32_t tmp = a;
+            a = b;
+            b = tmp;
+            tmp = wa;
+            wa = wb;
+            wb = tmp;
+        }
+        uint32_t expected = wb;
+        if (__hip_atomic_compare_exchange_strong(&lab[b], &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        b = wg_find(lab, b, &wb);
+        a = wg_find(lab, a, &wa);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_block_merge(SweepArgs a) {
+    const int L = a.L;
+    const int txa = blockIdx.x * kMergeTiles, tya = blockIdx.y * kMergeTiles;
+    const int ntx = min(kMergeTiles, a.tiles_x - txa), nty = min(kMergeTiles, a.tiles_y - tya);
+    const int ya = tya * kTileH, xa = txa * kTileW;
+    const int nrows = min((tya + nty) * kTileH, L) - ya;
+    const int ncols = min((txa + ntx) * kTileW, L) - xa;
+    const int nv = (ntx - 1) * nrows;  // bonds across the block's inner vertical tile borders
+    const int nh = (nty - 1) * ncols;
+    for (int k = threadIdx.x; k < nv + nh; k += blockDim.x) {
+        BorderBond b;
+        if (k < nv)
+            b = vertical_border_bond(a, txa + k / nrows, ya + k % nrows);
+        else
+            b = horizontal_border_bond(a, tya + (k - nv) / ncols, xa + (k - nv) % ncols);
+        if (b.active) wg_union(a.labels, b.i, b.j);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Merge, level 2: bonds across block borders and the periodic wrap, with the
+// device-wide lock-free union.  Thread g < nbx*L: right edge of the last tile
+// column of block column g / L; the rest: bottom edges of block rows.
+// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
-    const BorderBond b = border_bond(a, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+    const int L = a.L;
+    const int nbx = (a.tiles_x + kMergeTiles - 1) / kMergeTiles;
+    const int nby = (a.tiles_y + kMergeTiles - 1) / kMergeTiles;
+    const size_t gid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const size_t nv = static_cast<size_t>(nbx) * L;
+    BorderBond b{false, 0u, 0u};
+    if (gid < nv) {
+        const int bx = static_cast<int>(gid / L);
+        b = vertical_border_bond(a, min(bx * kMergeTiles + kMergeTiles - 1, a.tiles_x - 1), static_cast<int>(gid % L));
+    } else if (gid < nv + static_cast<size_t>(nby) * L) {
+        const size_t h = gid - nv;
+        const int by = static_cast<int>(h / L);
+        b = horizontal_border_bond(a, min(by * kMergeTiles + kMergeTiles - 1, a.tiles_y - 1), static_cast<int>(h % L));
+    }
     if (b.active) g_union(a.labels, b.i, b.j);
 }
 
@@ -459,12 +662,24 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bond_local, dim3(a.tiles_x, a.tiles_y), dim3(kBlock), 0, s, a);
+    if (a.model == 1)
+        hipLaunchKernelGGL(k_bond_local<1>, dim3(a.tiles_x, a.tiles_y), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_bond_local<0>, dim3(a.tiles_x, a.tiles_y), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_merge(const SweepArgs& a, hipStream_t s) {
+    const unsigned nbx = static_cast<unsigned>((a.tiles_x + kMergeTiles - 1) / kMergeTiles);
+    const unsigned nby = static_cast<unsigned>((a.tiles_y + kMergeTiles - 1) / kMergeTiles);
+    hipLaunchKernelGGL(k_block_merge, dim3(nbx, nby), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s) {
-    const size_t n = (static_cast<size_t>(a.tiles_x) + a.tiles_y) * a.L;
+    const unsigned nbx = static_cast<unsigned>((a.tiles_x + kMergeTiles - 1) / kMergeTiles);
+    const unsigned nby = static_cast<unsigned>((a.tiles_y + kMergeTiles - 1) / kMergeTiles);
+    const size_t n = (static_cast<size_t>(nbx) + nby) * a.L;
     hipLaunchKernelGGL(k_border_merge, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -350,6 +350,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         }
         st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(c->args, c->stream); });
         if (st) return st;
+        st = timed(c, profile, kKBlockMerge, [&] { return launch_block_merge(c->args, c->stream); });
+        if (st) return st;
         st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(c->args, c->stream); });
         if (st) return st;
         st = timed(c, profile, kKFlatten, [&] { return launch_flatten(c->args, c->stream); });
