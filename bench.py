@@ -107,8 +107,86 @@ def cpu_baseline(cfg, budget_s: float) -> dict:
             "sample": f"first {n} sweeps of {cfg.name} from the random start (single-threaded C oracle)"}
 
 
+def bench_batch(args) -> dict:
+    """256 q = 3 Potts replicas (L cycling over 64..512, T over [0.9, 1.1] T_c), 500
+    sweeps: batched launches + captured sweep graph, schedule picked by the
+    autotuner, against the same replicas swept one lattice per launch."""
+    import torch
+
+    import paper_1202_0635_amd as swmc
+    from paper_1202_0635_amd.workloads import replica_mix_q3
+
+    reps = replica_mix_q3(args.replicas)
+    sweeps = args.steps
+    specs = [(c.L, c.q, c.model, c.T, c.J, c.seed) for c in reps]
+    sites = sum(c.L * c.L for c in reps)
+    b = swmc.Batch(specs)
+    chosen = b.tune(5)
+    b.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(sweeps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    # the plain path: one lattice per launch, replicas one after another
+    lats = [swmc.Lattice(*sp[:3], T=sp[3], J=sp[4], seed=sp[5]) for sp in specs]
+    for lat in lats:
+        lat.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.sweep(sweeps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for lat in lats:
+        lat.close()
+    return {"metric": "batched vs plain speedup (SW sweep, replica mix)", "value": t_plain / t_batch, "unit": "x",
+            "higher_is_better": True, "n_gpus": 1, "steps": sweeps, "warmup": args.warmup, "dtype": "int8",
+            "data": "synthetic",
+            "config": {"workload": "potts3_replicas_256_L64-512", "replicas": len(reps), "sites": sites,
+                       "merge_tiles": chosen},
+            "batched_spin_updates_per_s": sites * sweeps / t_batch,
+            "plain_spin_updates_per_s": sites * sweeps / t_plain,
+            "batched_ns_per_update": t_batch * 1e9 / (sites * sweeps), "batched_s": t_batch, "plain_s": t_plain}
+
+
+def bench_serve(args) -> dict:
+    """Request trace (L log-uniform in [128, 2048], Potts q = 2, 3, 4 or clock q = 6,
+    T in [0.8, 1.2] T_c, 100-1000 sweeps): capacity from a saturation run, then
+    Poisson arrivals at 0.8 x capacity through the continuous-batching server
+    and through the one-lattice-per-launch path."""
+    import paper_1202_0635_amd  # noqa: F401
+    from paper_1202_0635_amd import serve
+    from paper_1202_0635_amd.workloads import request_trace
+
+    trace = request_trace(args.requests)
+    budget = int(args.budget_gib * (1 << 30))
+    sat = serve.run_trace(trace, serve.poisson_arrivals(len(trace), 0.0), budget, args.slots, args.sweeps_per_step)
+    capacity = len(trace) / sat["makespan_s"]
+    arrivals = serve.poisson_arrivals(len(trace), 0.8 * capacity, seed=20120203)
+    served = serve.run_trace(trace, arrivals, budget, args.slots, args.sweeps_per_step)
+    plain = serve.run_plain(trace, arrivals)
+    same = all(served["results"][i]["spin_hash"] == plain["results"][i]["spin_hash"] for i in range(len(trace)))
+    strip = lambda d: {k: v for k, v in d.items() if k not in ("results", "stats")}
+    return {"metric": "served vs plain throughput (SW requests, continuous batching)",
+            "value": served["spin_updates_per_s"] / plain["spin_updates_per_s"], "unit": "x",
+            "higher_is_better": True, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
+            "config": {"workload": f"request_trace_{len(trace)}", "budget_bytes": budget, "slots": args.slots,
+                       "sweeps_per_step": args.sweeps_per_step, "arrival_rate_per_s": 0.8 * capacity},
+            "saturation": strip(sat), "served": strip(served), "plain": strip(plain),
+            "results_identical": same}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=["sweep", "batch", "serve"], default="sweep",
+                    help="sweep: one L=4096 lattice (default); batch: replica mix; serve: request trace")
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--budget-gib", type=float, default=2.0)
+    ap.add_argument("--slots", type=int, default=128)
+    ap.add_argument("--sweeps-per-step", type=int, default=25)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
@@ -125,6 +203,13 @@ def main() -> int:
 
     import torch
 
+    if args.mode == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
+    if args.mode == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
+        return 0
+
     import paper_1202_0635_amd as swmc
     from paper_1202_0635_amd.workloads import CONFIGS
 
@@ -133,6 +218,8 @@ def main() -> int:
     N = cfg.L * cfg.L
     lat = swmc.Lattice(cfg.L, cfg.q, cfg.model, T=cfg.T, J=cfg.J, seed=cfg.seed)
     lat.sweep(args.warmup)
+    # the autotuner picks the merge schedule on the warmed-up state and restores it
+    schedule = lat.tune(5)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -169,7 +256,8 @@ def main() -> int:
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": cfg.name, "L": cfg.L, "q": cfg.q, "model": cfg.model, "T": cfg.T, "J": cfg.J,
-                   "seed": cfg.seed, "warmup_sweeps": args.warmup, "timed_sweeps": args.steps},
+                   "seed": cfg.seed, "warmup_sweeps": args.warmup, "timed_sweeps": args.steps,
+                   "merge_tiles": schedule},
         "spin_updates_per_s": N * args.steps / (ms * 1e-3),
         "sweep_alg_GBps": sweep_gbps,
         "kernels": kernels,

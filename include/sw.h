@@ -57,7 +57,8 @@ typedef enum { SW_POTTS = 0, SW_CLOCK = 1 } sw_model;
 enum {
     SW_MEASURE = 1u, /* accumulate E, M^2, M^4 after every sweep of this call */
     SW_VERIFY = 2u,  /* also store the canonical labels of the last sweep */
-    SW_PROFILE = 4u  /* time every kernel launch with HIP events (read by sw_profile_read) */
+    SW_PROFILE = 4u, /* time every kernel launch with HIP events (read by sw_profile_read) */
+    SW_NO_GRAPH = 8u /* batches: launch the kernels directly instead of replaying the captured sweep */
 };
 
 /* One lattice.  Potts: H = -J sum_<ij> (delta(S_i,S_j) - 1) (Sec. 2, Eq. 1);
@@ -136,9 +137,98 @@ int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n);
 int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* total_ms,
                     int32_t cap, int32_t* nk);
 
+/* Schedule: tiles per side of the blocks whose inner borders the first merge
+ * level joins (1 = single-level merge; 1, 2, 4 or 8).  Results do not depend on
+ * it (canonical labels are unique); only the time does. */
+int sw_set_schedule(sw_ctx* c, int32_t merge_tiles);
+/* Autotuner: times `sweeps` sweeps under every schedule from the current state,
+ * restores the state (spins and sweep index) after each, keeps the fastest and
+ * returns it in *merge_tiles.  Allocates a temporary snapshot buffer. */
+int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles);
+
 void sw_free(sw_ctx* c);
 const char* sw_strerror(int status);
 const char* sw_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Batches: n independent lattices (replicas of any L, q, model, T, seed) swept
+ * together.  Every phase of a sweep (Sec. 2 steps (1)-(3)) is one launch over
+ * the workgroups of all replicas; one sweep's launches are captured once in a
+ * hipGraph and replayed.  Each replica's chain is bit-identical to the same
+ * lattice run alone through sw_init/sw_sweep.
+ * ------------------------------------------------------------------------- */
+typedef struct sw_batch sw_batch;
+
+/* Device bytes for the batch arena (replica states + launch maps); 0 if any
+ * lattice is invalid or n is not in [1, 65535]. */
+size_t sw_batch_bytes(const sw_lattice* ps, int32_t n);
+/* ps[n] as in sw_init; dev_mem caller-owned (256-byte aligned, at least
+ * sw_batch_bytes) or NULL (library-owned).  Random start for every replica. */
+int sw_batch_init(const sw_lattice* ps, int32_t n, void* dev_mem, size_t bytes, void* stream, sw_batch** out);
+/* nsweeps sweeps of every replica; flags SW_MEASURE | SW_VERIFY | SW_PROFILE |
+ * SW_NO_GRAPH (the graph is used only without SW_MEASURE and SW_PROFILE). */
+int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags);
+/* Per replica, as sw_measure / sw_read_spins / sw_read_labels (synchronous). */
+int sw_batch_measure(sw_batch* b, int32_t replica, sw_obs* out);
+int sw_batch_read_spins(sw_batch* b, int32_t replica, int8_t* host, size_t n);
+int sw_batch_read_labels(sw_batch* b, int32_t replica, int32_t* host, size_t n);
+int32_t sw_batch_size(sw_batch* b);
+int sw_batch_set_schedule(sw_batch* b, int32_t merge_tiles);
+int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles);
+int sw_batch_profile_read(sw_batch* b, const char** names, int64_t* launches, double* total_ms, int32_t cap,
+                          int32_t* nk);
+void sw_batch_free(sw_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of simulation requests.  A request is one
+ * lattice and a sweep count.  Requests wait in arrival order; at every step
+ * the server admits waiting requests while their state fits the device-memory
+ * budget and a slot is free (a request that cannot fit waits at the head of
+ * the queue), then runs sweeps_per_step sweeps over every active lattice as
+ * one batched launch per phase (a lattice that reaches its sweep count sits
+ * the rest of the step out), then retires the finished ones: their final
+ * observables and spin hash become results and their memory is freed.  Each
+ * result is identical to running that lattice alone.  The caller drives the
+ * server (submit / step / poll); a server is not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct sw_server sw_server;
+
+typedef struct {
+    sw_lattice lattice;
+    int64_t sweeps;   /* sweeps from the random start, >= 1 */
+    uint64_t tag;     /* caller's id, returned with the result */
+    double t_arrival; /* arrival time on the server clock (sw_server_now); latency counts from it */
+} sw_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;     /* SW_OK, or SW_EBUDGET: the request can never fit the budget */
+    int32_t reserved;
+    sw_obs obs;         /* observables of the final state (obs.sweeps_done == sweeps) */
+    uint64_t spin_hash; /* sum over sites of SplitMix64-finalised ((i << 8) | s_i), mod 2^64 */
+    double t_arrival, t_admit, t_done;
+} sw_result;
+
+typedef struct {
+    int64_t submitted, waiting, active, completed, rejected, steps;
+    int64_t spin_updates; /* sum of L^2 * sweeps over completed requests */
+    uint64_t budget_bytes, used_bytes;
+} sw_server_stats;
+
+/* budget_bytes: device memory for lattice states (allocated once here);
+ * max_slots >= 1 lattices at a time; sweeps_per_step >= 1. */
+int sw_server_create(uint64_t budget_bytes, int32_t max_slots, int32_t sweeps_per_step, void* stream,
+                     sw_server** out);
+double sw_server_now(sw_server* s);
+/* Queue a request (SW_EINVAL for an invalid lattice or sweeps < 1; a request
+ * larger than the whole budget is completed at once with status SW_EBUDGET). */
+int sw_server_submit(sw_server* s, const sw_request* req);
+/* Admit, run one step, retire; synchronous.  *active = lattices that ran. */
+int sw_server_step(sw_server* s, int32_t* active);
+/* Move up to cap finished results to out[]; *n = how many. */
+int sw_server_poll(sw_server* s, sw_result* out, int32_t cap, int32_t* n);
+int sw_server_stats_read(sw_server* s, sw_server_stats* out);
+void sw_server_destroy(sw_server* s);
 
 #ifdef __cplusplus
 }

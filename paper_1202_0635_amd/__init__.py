@@ -14,10 +14,10 @@ import math
 import numpy as np
 
 from . import _lib
-from ._lib import SW_CLOCK, SW_MEASURE, SW_POTTS, SW_PROFILE, SW_VERIFY, SwError, SwLattice, SwObs, check
+from ._lib import SW_CLOCK, SW_MEASURE, SW_NO_GRAPH, SW_POTTS, SW_PROFILE, SW_VERIFY, SwError, SwLattice, SwObs, check
 
-__all__ = ["Lattice", "SwError", "critical_temperature", "cutoff_table", "state_bytes",
-           "SW_MEASURE", "SW_VERIFY", "SW_PROFILE"]
+__all__ = ["Lattice", "Batch", "SwError", "critical_temperature", "cutoff_table", "state_bytes",
+           "SW_MEASURE", "SW_VERIFY", "SW_PROFILE", "SW_NO_GRAPH"]
 
 MODELS = {"potts": SW_POTTS, "clock": SW_CLOCK}
 
@@ -138,6 +138,15 @@ class Lattice:
         check(_lib.lib().sw_profile_read(self._ctx, names, launches, ms, 8, ctypes.byref(nk)), "sw_profile_read")
         return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(nk.value)}
 
+    def set_schedule(self, merge_tiles: int):
+        check(_lib.lib().sw_set_schedule(self._ctx, int(merge_tiles)), "sw_set_schedule")
+        return self
+
+    def tune(self, sweeps: int = 5) -> int:
+        out = ctypes.c_int32()
+        check(_lib.lib().sw_tune(self._ctx, int(sweeps), ctypes.byref(out)), "sw_tune")
+        return int(out.value)
+
     def synchronize(self):
         self._stream.synchronize()
 
@@ -145,6 +154,113 @@ class Lattice:
         if getattr(self, "_ctx", None):
             _lib.lib().sw_free(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _obs_dict(o: SwObs, q: int) -> dict:
+    return {
+        "t": int(o.sweeps_done), "samples": int(o.samples),
+        "hist": np.array(o.hist[:q], dtype=np.int64), "pair_hist": np.array(o.pair_hist[:q], dtype=np.int64),
+        "e": o.e_per_site, "m2": o.m2, "mean_e": o.mean_e, "mean_m2": o.mean_m2,
+        "mean_m4": o.mean_m4, "binder_u": o.binder_u,
+    }
+
+
+class Batch:
+    """Many independent lattices swept together (one launch per phase for all
+    of them, a captured hipGraph per sweep).  `specs` is a list of dicts or
+    tuples (L, q, model, T, J, seed)."""
+
+    def __init__(self, specs, device=None, stream=None):
+        import torch
+
+        ps = []
+        self.specs = []
+        for sp in specs:
+            if isinstance(sp, dict):
+                L, q, model = sp["L"], sp["q"], sp.get("model", "potts")
+                T = sp.get("T") or critical_temperature(model, q)
+                J, seed = sp.get("J", 1.0), sp.get("seed", 0)
+            else:
+                L, q, model, T, J, seed = sp
+            self.specs.append((int(L), int(q), model, float(T), float(J), int(seed)))
+            ps.append(_lattice(L, q, model, T, J, seed))
+        n = len(ps)
+        self._ps = (SwLattice * n)(*ps)
+        lib = _lib.lib()
+        nbytes = int(lib.sw_batch_bytes(self._ps, n))
+        if nbytes == 0:
+            check(_lib.SW_EINVAL, "sw_batch_bytes")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self._arena.data_ptr() + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        b = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            check(lib.sw_batch_init(self._ps, n, ctypes.c_void_p(aligned), nbytes,
+                                    ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(b)), "sw_batch_init")
+        self._b = b
+        self.n = n
+
+    def __len__(self):
+        return self.n
+
+    def sweep(self, n: int = 1, measure: bool = False, verify: bool = False, profile: bool = False,
+              graph: bool = True):
+        flags = ((SW_MEASURE if measure else 0) | (SW_VERIFY if verify else 0) | (SW_PROFILE if profile else 0)
+                 | (0 if graph else SW_NO_GRAPH))
+        check(_lib.lib().sw_batch_sweep(self._b, int(n), flags), "sw_batch_sweep")
+        return self
+
+    def measure(self, r: int) -> dict:
+        o = SwObs()
+        check(_lib.lib().sw_batch_measure(self._b, int(r), ctypes.byref(o)), "sw_batch_measure")
+        return _obs_dict(o, self.specs[r][1])
+
+    def spins(self, r: int) -> np.ndarray:
+        L = self.specs[r][0]
+        out = np.zeros(L * L, dtype=np.int8)
+        check(_lib.lib().sw_batch_read_spins(self._b, int(r), out.ctypes.data_as(ctypes.c_void_p), L * L),
+              "sw_batch_read_spins")
+        return out.reshape(L, L)
+
+    def labels(self, r: int) -> np.ndarray:
+        L = self.specs[r][0]
+        out = np.zeros(L * L, dtype=np.int32)
+        check(_lib.lib().sw_batch_read_labels(self._b, int(r), out.ctypes.data_as(ctypes.c_void_p), L * L),
+              "sw_batch_read_labels")
+        return out.reshape(L, L)
+
+    def set_schedule(self, merge_tiles: int):
+        check(_lib.lib().sw_batch_set_schedule(self._b, int(merge_tiles)), "sw_batch_set_schedule")
+        return self
+
+    def tune(self, sweeps: int = 5) -> int:
+        out = ctypes.c_int32()
+        check(_lib.lib().sw_batch_tune(self._b, int(sweeps), ctypes.byref(out)), "sw_batch_tune")
+        return int(out.value)
+
+    def profile(self) -> dict:
+        names = (ctypes.c_char_p * 8)()
+        launches = (ctypes.c_int64 * 8)()
+        ms = (ctypes.c_double * 8)()
+        nk = ctypes.c_int32()
+        check(_lib.lib().sw_batch_profile_read(self._b, names, launches, ms, 8, ctypes.byref(nk)),
+              "sw_batch_profile_read")
+        return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(nk.value)}
+
+    def synchronize(self):
+        self._stream.synchronize()
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.lib().sw_batch_free(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_PKG, "libswmc.so")
 
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_ESTATE, SW_EBUDGET, SW_EBUSY = 0, -1, -2, -3, -4, -5, -6
 SW_POTTS, SW_CLOCK = 0, 1
-SW_MEASURE, SW_VERIFY, SW_PROFILE = 1, 2, 4
+SW_MEASURE, SW_VERIFY, SW_PROFILE, SW_NO_GRAPH = 1, 2, 4, 8
 
 
 class SwLattice(ctypes.Structure):
@@ -39,6 +39,23 @@ class SwObs(ctypes.Structure):
     ]
 
 
+class SwRequest(ctypes.Structure):
+    _fields_ = [("lattice", SwLattice), ("sweeps", ctypes.c_int64), ("tag", ctypes.c_uint64),
+                ("t_arrival", ctypes.c_double)]
+
+
+class SwResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("obs", SwObs), ("spin_hash", ctypes.c_uint64), ("t_arrival", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class SwServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("waiting", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("spin_updates", ctypes.c_int64), ("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64)]
+
+
 class SwError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: {detail} (status {status})")
@@ -63,7 +80,32 @@ SIGNATURES = {
     "sw_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "sw_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "sw_free": (None, [ctypes.c_void_p]),
+    "sw_batch_bytes": (ctypes.c_size_t, [ctypes.POINTER(SwLattice), ctypes.c_int32]),
+    "sw_batch_init": (ctypes.c_int, [ctypes.POINTER(SwLattice), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_batch_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
+    "sw_batch_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SwObs)]),
+    "sw_batch_read_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_batch_read_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_batch_size": (ctypes.c_int32, [ctypes.c_void_p]),
+    "sw_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "sw_batch_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p),
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "sw_batch_free": (None, [ctypes.c_void_p]),
+    "sw_server_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "sw_server_now": (ctypes.c_double, [ctypes.c_void_p]),
+    "sw_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwRequest)]),
+    "sw_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "sw_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwResult), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "sw_server_stats_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwServerStats)]),
+    "sw_server_destroy": (None, [ctypes.c_void_p]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error": (ctypes.c_char_p, []),
 }

@@ -1,0 +1,50 @@
+// Host-side helpers shared by the single-lattice and the batched runtimes.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sw.h"
+#include "sw_internal.hpp"
+
+namespace swmc {
+namespace host {
+
+// Record a status with a formatted reason (thread-local, read by sw_last_error).
+int fail(int status, const char* fmt, ...);
+bool lattice_ok(const sw_lattice* p, std::string* why);
+
+double turn_cos(int n, int q);
+double turn_sin(int n, int q);
+size_t table_entries(const sw_lattice& p);
+void build_table(const sw_lattice& p, uint32_t* out);
+
+constexpr size_t kAlign = 256;
+size_t up(size_t v);
+
+struct Layout {
+    size_t ctl, spins, bond_r, bond_d, labels, canon, ring, scratch_row, table, total;
+};
+Layout layout_of(const sw_lattice& p);
+
+struct Observables {
+    double e = 0.0, m2 = 0.0;
+};
+Observables observables_of(const sw_lattice& p, const int64_t* row);
+void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, uint64_t samples, double sum_e, double sum_m2,
+              double sum_m4, sw_obs* out);
+
+SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay);
+// Control block of a fresh lattice: t = 0, no sweep target.
+extern const Control kFreshControl;
+
+// Launch lists of the batched kernels: one launch per list and sweep covers
+// the workgroups of every lattice in a set.
+enum ListId { kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip, kLCounts, kNumLists };
+// Workgroups list l needs for one lattice.
+uint32_t blocks_for(int l, const SweepArgs& a);
+
+}  // namespace host
+}  // namespace swmc

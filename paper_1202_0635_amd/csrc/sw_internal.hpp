@@ -14,8 +14,11 @@ constexpr int kTileW = 64;
 constexpr int kTileH = 64;
 constexpr int kWaves = 4;
 constexpr int kBlock = kWaves * 64;
-// Tiles per side of the blocks whose inner borders the first merge level joins.
+// Default tiles per side of the blocks whose inner borders the first merge
+// level joins (a per-context schedule parameter, see the autotuner).
 constexpr int kMergeTiles = 4;
+// Threads of a first-level merge workgroup.
+constexpr int kMergeThreads = 1024;
 
 // Random-number purposes (third counter word of a Philox draw).
 constexpr uint32_t kBondHi = 0;
@@ -36,9 +39,12 @@ constexpr int kRowWords = 64;    // int64 per count row: hist[32], pair_hist[32]
 // Device control block at the start of the arena.
 struct Control {
     uint64_t t;       // sweep index of the current state
+    uint64_t target;  // sweeps stop once t reaches this (all ones: never)
     uint32_t mirror;  // clock model: mirror index of the sweep in progress
-    uint32_t pad[13];
+    uint32_t live;    // the sweep in progress runs (t < target when it started)
+    uint32_t pad[10];
 };
+static_assert(sizeof(Control) == 64, "control block is one 64-byte line");
 
 struct SweepArgs {
     int8_t* spins;        // [N]
@@ -51,6 +57,7 @@ struct SweepArgs {
     int64_t* count_row;   // destination row of the count kernel (or null)
     int L, q, model, w64;
     int tiles_x, tiles_y;
+    int merge_tiles;      // tiles per side of a first-level merge block (1: no block level)
     uint32_t key0, key1;
 };
 
@@ -62,6 +69,26 @@ hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s);
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s);
+
+// Workgroups of each launch for one lattice.
+__host__ __device__ inline uint32_t count_blocks(int L) {
+    const uint64_t n = (static_cast<uint64_t>(L) * L + 255) / 256;
+    return static_cast<uint32_t>(n < 1024 ? n : 1024);
+}
+__host__ __device__ inline uint32_t merge_blocks_x(int tiles_x, int mt) { return static_cast<uint32_t>((tiles_x + mt - 1) / mt); }
+
+// Batched launches: one launch covers the workgroups of every replica.
+enum BatchKernel {
+    kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge, kBKFlatten, kBKFlip, kBKFlipVerify, kBKCounts,
+    kNumBatchKernels
+};
+struct BatchLaunch {
+    const SweepArgs* reps;  // device replica table
+    const uint32_t* map;    // device: workgroup -> replica
+    const uint32_t* begin;  // device: replica -> first workgroup of this launch
+    uint32_t blocks;        // workgroups of the launch
+};
+hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint32_t row);
 
 enum KernelId { kKBondLocal = 0, kKBlockMerge = 1, kKBorderMerge = 2, kKFlatten = 3, kKFlip = 4, kKCounts = 5, kNumKernels = 6 };
 extern const char* const kKernelNames[kNumKernels];

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_init(SweepArgs a) {
 // collected in a tile-wide list and resolved with one draw per tied site.
 // ---------------------------------------------------------------------------
 template <int kModel>
-__global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
+__device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty) {
     constexpr bool kClock = kModel == 1;
     constexpr int RPW = kTileH / kWaves;  // rows per wave
     static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
@@ -186,7 +186,6 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int L = a.L, q = a.q;
-    const int tx = blockIdx.x, ty = blockIdx.y;
     const int x0 = tx * kTileW, y0 = ty * kTileH;
     const int x = x0 + lane;
     const bool col_ok = x < L;
@@ -195,6 +194,11 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     const uint64_t in_tile_r = (nvalid >= 64) ? (~0ull >> 1) : ((1ull << (nvalid - 1)) - 1ull);
     const uint64_t t = a.ctl->t;
     const uint32_t k0 = a.key0, k1 = a.key1;
+    // A lattice whose sweep target is reached sits this sweep out; the later
+    // kernels of the sweep read the decision from the control block.
+    const bool live = t < a.ctl->target;
+    if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->live = live ? 1u : 0u;
+    if (!live) return;
 
     // Cutoffs of this sweep: Potts needs only the equal-spin cutoff; the clock
     // model reads the q x q slice of its mirror m from LDS.
@@ -374,9 +378,12 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
         const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
         const uint32_t root = rootreg[r];
         const bool is_root = ok && (root == self);
-        if (ok && !is_root)
+        // every site of the row is stored (a root gets a placeholder root word
+        // that its draw below overwrites), so label lines are written whole
+        if (ok)
             a.labels[static_cast<size_t>(y) * L + x] =
-                static_cast<uint32_t>((y0 + static_cast<int>(root >> 6)) * L + x0 + static_cast<int>(root & 63));
+                is_root ? kRootFlag
+                        : static_cast<uint32_t>((y0 + static_cast<int>(root >> 6)) * L + x0 + static_cast<int>(root & 63));
         const uint64_t rm = __ballot(is_root);
         if (is_root)
             list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] = static_cast<uint32_t>(y * L + x);
@@ -492,10 +499,12 @@ __device__ void wg_union(uint32_t* lab, uint32_t a, uint32_t b) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_block_merge(SweepArgs a) {
+__device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, const int by) {
+    if (!a.ctl->live) return;
     const int L = a.L;
-    const int txa = blockIdx.x * kMergeTiles, tya = blockIdx.y * kMergeTiles;
-    const int ntx = min(kMergeTiles, a.tiles_x - txa), nty = min(kMergeTiles, a.tiles_y - tya);
+    const int mt = a.merge_tiles;
+    const int txa = bx * mt, tya = by * mt;
+    const int ntx = min(mt, a.tiles_x - txa), nty = min(mt, a.tiles_y - tya);
     const int ya = tya * kTileH, xa = txa * kTileW;
     const int nrows = min((tya + nty) * kTileH, L) - ya;
     const int ncols = min((txa + ntx) * kTileW, L) - xa;
@@ -516,20 +525,21 @@ __global__ void __launch_bounds__(256) k_block_merge(SweepArgs a) {
 // device-wide lock-free union.  Thread g < nbx*L: right edge of the last tile
 // column of block column g / L; the rest: bottom edges of block rows.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
+__device__ __forceinline__ void border_merge(const SweepArgs& a, const size_t gid) {
+    if (!a.ctl->live) return;
     const int L = a.L;
-    const int nbx = (a.tiles_x + kMergeTiles - 1) / kMergeTiles;
-    const int nby = (a.tiles_y + kMergeTiles - 1) / kMergeTiles;
-    const size_t gid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int mt = a.merge_tiles;
+    const int nbx = (a.tiles_x + mt - 1) / mt;
+    const int nby = (a.tiles_y + mt - 1) / mt;
     const size_t nv = static_cast<size_t>(nbx) * L;
     BorderBond b{false, 0u, 0u};
     if (gid < nv) {
         const int bx = static_cast<int>(gid / L);
-        b = vertical_border_bond(a, min(bx * kMergeTiles + kMergeTiles - 1, a.tiles_x - 1), static_cast<int>(gid % L));
+        b = vertical_border_bond(a, min(bx * mt + mt - 1, a.tiles_x - 1), static_cast<int>(gid % L));
     } else if (gid < nv + static_cast<size_t>(nby) * L) {
         const size_t h = gid - nv;
         const int by = static_cast<int>(h / L);
-        b = horizontal_border_bond(a, min(by * kMergeTiles + kMergeTiles - 1, a.tiles_y - 1), static_cast<int>(h % L));
+        b = horizontal_border_bond(a, min(by * mt + mt - 1, a.tiles_y - 1), static_cast<int>(h % L));
     }
     if (b.active) g_union(a.labels, b.i, b.j);
 }
@@ -560,11 +570,12 @@ __device__ __forceinline__ void flatten_from(uint32_t* lab, uint32_t e) {
     lab[r] = x;
 }
 
-__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) {
+__device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block) {
+    if (!a.ctl->live) return;
     // Every kernel that reads the sweep index has finished (stream order); the
     // flip only needs the mirror recorded by k_bond_local.
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->t += 1;
-    const BorderBond b = border_bond(a, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+    if (block == 0 && threadIdx.x == 0) a.ctl->t += 1;
+    const BorderBond b = border_bond(a, static_cast<size_t>(block) * blockDim.x + threadIdx.x);
     if (!b.active) return;
     flatten_from(a.labels, b.i);
     flatten_from(a.labels, b.j);
@@ -574,54 +585,74 @@ __global__ void __launch_bounds__(256) k_flatten(SweepArgs a) {
 // Cluster flip, four sites per thread.
 // ---------------------------------------------------------------------------
 template <bool kVerify>
-__global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
-    const size_t N = static_cast<size_t>(a.L) * a.L;
-    const size_t base = (static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
-    const bool clock = a.model == 1;
-    if (base < N) {
-        const int n = (N - base >= 4) ? 4 : static_cast<int>(N - base);
-        uint32_t x[4], w[4];
-        if (n == 4) {
-            const uint4 v = *reinterpret_cast<const uint4*>(a.labels + base);
-            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-        } else {
-            for (int k = 0; k < 4; ++k) w[k] = (k < n) ? a.labels[base + k] : kRootFlag;
+__device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int ty) {
+    // One 64 x 64 tile per workgroup: thread t takes 16 consecutive sites of
+    // row t/4, so the tile-local root words its sites point to were just read
+    // by the same workgroup.
+    if (!a.ctl->live) return;
+    const int L = a.L;
+    const int y = ty * kTileH + static_cast<int>(threadIdx.x >> 2);
+    const int xs = tx * kTileW + static_cast<int>(threadIdx.x & 3) * 16;
+    if (y >= L || xs >= L) return;
+    const int nx = min(16, L - xs);
+    const size_t base = static_cast<size_t>(y) * L + xs;
+    const bool full = (nx == 16) && ((base & 3) == 0);
+    uint32_t x[16], w[16];
+    if (full) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint4 v = *reinterpret_cast<const uint4*>(a.labels + base + 4 * g);
+            w[4 * g] = v.x; w[4 * g + 1] = v.y; w[4 * g + 2] = v.z; w[4 * g + 3] = v.w;
         }
+    } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = static_cast<uint32_t>(base + k);
-        // follow the four paths together (independent loads in flight)
-        while (!((w[0] & w[1] & w[2] & w[3]) & kRootFlag)) {
+        for (int k = 0; k < 16; ++k) w[k] = (k < nx) ? a.labels[base + k] : kRootFlag;
+    }
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (!(w[k] & kRootFlag)) {
-                    x[k] = w[k];
-                    w[k] = a.labels[x[k]];
-                }
-        }
-        uint32_t out[4];
-        if (!clock) {
+    for (int k = 0; k < 16; ++k) x[k] = static_cast<uint32_t>(base + k);
+    // follow the sixteen paths together (independent loads in flight)
+    bool pending = true;
+    while (pending) {
+        pending = false;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) out[k] = w[k] & 0xFFu;
-        } else {
-            const int m = static_cast<int>(a.ctl->mirror);
-            for (int k = 0; k < 4; ++k) {
-                int s = (k < n) ? a.spins[base + k] : 0;
-                if (w[k] & 1u) {
-                    s = m - s;
-                    if (s < 0) s += a.q;
-                }
-                out[k] = static_cast<uint32_t>(s);
+        for (int k = 0; k < 16; ++k)
+            if (!(w[k] & kRootFlag)) {
+                x[k] = w[k];
+                w[k] = a.labels[x[k]];
+                pending = true;
             }
+    }
+    uint32_t out[16];
+    if (a.model == 0) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) out[k] = w[k] & 0xFFu;
+    } else {
+        const int m = static_cast<int>(a.ctl->mirror);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            int sp = (k < nx) ? a.spins[base + k] : 0;
+            if (w[k] & 1u) {
+                sp = m - sp;
+                if (sp < 0) sp += a.q;
+            }
+            out[k] = static_cast<uint32_t>(sp);
         }
-        if (n == 4) {
-            *reinterpret_cast<uint32_t*>(a.spins + base) = out[0] | (out[1] << 8) | (out[2] << 16) | (out[3] << 24);
-            if (kVerify) *reinterpret_cast<uint4*>(a.canon + base) = make_uint4(x[0], x[1], x[2], x[3]);
-        } else {
-            for (int k = 0; k < n; ++k) {
+    }
+    if (full) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            *reinterpret_cast<uint32_t*>(a.spins + base + 4 * g) =
+                out[4 * g] | (out[4 * g + 1] << 8) | (out[4 * g + 2] << 16) | (out[4 * g + 3] << 24);
+            if (kVerify)
+                *reinterpret_cast<uint4*>(a.canon + base + 4 * g) = make_uint4(x[4 * g], x[4 * g + 1], x[4 * g + 2], x[4 * g + 3]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < nx) {
                 a.spins[base + k] = static_cast<int8_t>(out[k]);
                 if (kVerify) a.canon[base + k] = x[k];
             }
-        }
     }
 }
 
@@ -629,14 +660,14 @@ __global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
 // Integer counts of the current state: n[k] and the owned-bond histogram of
 // (s_j - s_i) mod q, accumulated into one int64 row.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_counts(SweepArgs a) {
+__device__ __forceinline__ void counts(const SweepArgs& a, int64_t* row, const uint32_t block, const uint32_t nblocks) {
     __shared__ uint32_t h[kRowWords];
     for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) h[k] = 0;
     __syncthreads();
     const int L = a.L, q = a.q;
     const size_t N = static_cast<size_t>(L) * L;
-    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    for (size_t i = static_cast<size_t>(block) * blockDim.x + threadIdx.x; i < N;
+         i += static_cast<size_t>(nblocks) * blockDim.x) {
         const int y = static_cast<int>(i / L), x = static_cast<int>(i % L);
         const int s = a.spins[i];
         const int sr = a.spins[static_cast<size_t>(y) * L + ((x + 1 == L) ? 0 : x + 1)];
@@ -650,7 +681,81 @@ __global__ void __launch_bounds__(256) k_counts(SweepArgs a) {
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kRowWords; k += blockDim.x)
-        if (h[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.count_row[k]), static_cast<unsigned long long>(h[k]));
+        if (h[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&row[k]), static_cast<unsigned long long>(h[k]));
+}
+
+
+// ---------------------------------------------------------------------------
+// Entry points.  k_*: one lattice per launch.  kb_*: one launch covers every
+// replica of a batch; workgroup b serves replica map[b], local block
+// b - begin[replica].
+// ---------------------------------------------------------------------------
+template <int kModel>
+__global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) { bond_local_tile<kModel>(a, blockIdx.x, blockIdx.y); }
+
+__global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
+
+__global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
+    border_merge(a, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, blockIdx.x); }
+
+template <bool kVerify>
+__global__ void __launch_bounds__(256) k_flip(SweepArgs a) { flip<kVerify>(a, blockIdx.x, blockIdx.y); }
+
+__global__ void __launch_bounds__(256) k_counts(SweepArgs a) { counts(a, a.count_row, blockIdx.x, gridDim.x); }
+
+struct BatchMap {
+    const SweepArgs* reps;  // replica table
+    const uint32_t* map;    // workgroup -> replica
+    const uint32_t* begin;  // replica -> its first workgroup in this launch
+};
+
+__device__ __forceinline__ uint32_t batch_replica(const BatchMap& m, uint32_t* local) {
+    const uint32_t r = m.map[blockIdx.x];
+    *local = blockIdx.x - m.begin[r];
+    return r;
+}
+
+template <int kModel>
+__global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    bond_local_tile<kModel>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+}
+
+__global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    const int nbx = (a.tiles_x + a.merge_tiles - 1) / a.merge_tiles;
+    block_merge(a, static_cast<int>(local % nbx), static_cast<int>(local / nbx));
+}
+
+__global__ void __launch_bounds__(256) kb_border_merge(BatchMap m) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    border_merge(a, static_cast<size_t>(local) * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_flatten(BatchMap m) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    flatten(a, local);
+}
+
+template <bool kVerify>
+__global__ void __launch_bounds__(256) kb_flip(BatchMap m) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    flip<kVerify>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+}
+
+__global__ void __launch_bounds__(256) kb_counts(BatchMap m, uint32_t row) {
+    uint32_t local;
+    const uint32_t r = batch_replica(m, &local);
+    const SweepArgs& a = m.reps[r];
+    counts(a, a.count_row + static_cast<size_t>(row) * kRowWords, local, count_blocks(a.L));
 }
 
 }  // namespace
@@ -670,15 +775,16 @@ hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_block_merge(const SweepArgs& a, hipStream_t s) {
-    const unsigned nbx = static_cast<unsigned>((a.tiles_x + kMergeTiles - 1) / kMergeTiles);
-    const unsigned nby = static_cast<unsigned>((a.tiles_y + kMergeTiles - 1) / kMergeTiles);
-    hipLaunchKernelGGL(k_block_merge, dim3(nbx, nby), dim3(256), 0, s, a);
+    if (a.merge_tiles <= 1) return hipSuccess;
+    const unsigned nbx = static_cast<unsigned>((a.tiles_x + a.merge_tiles - 1) / a.merge_tiles);
+    const unsigned nby = static_cast<unsigned>((a.tiles_y + a.merge_tiles - 1) / a.merge_tiles);
+    hipLaunchKernelGGL(k_block_merge, dim3(nbx, nby), dim3(kMergeThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s) {
-    const unsigned nbx = static_cast<unsigned>((a.tiles_x + kMergeTiles - 1) / kMergeTiles);
-    const unsigned nby = static_cast<unsigned>((a.tiles_y + kMergeTiles - 1) / kMergeTiles);
+    const unsigned nbx = static_cast<unsigned>((a.tiles_x + a.merge_tiles - 1) / a.merge_tiles);
+    const unsigned nby = static_cast<unsigned>((a.tiles_y + a.merge_tiles - 1) / a.merge_tiles);
     const size_t n = (static_cast<size_t>(nbx) + nby) * a.L;
     hipLaunchKernelGGL(k_border_merge, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -691,8 +797,7 @@ hipError_t launch_flatten(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
-    const size_t N = static_cast<size_t>(a.L) * a.L;
-    const dim3 grid(static_cast<unsigned>((N + 1023) / 1024));
+    const dim3 grid(static_cast<unsigned>(a.tiles_x), static_cast<unsigned>(a.tiles_y));
     if (verify)
         hipLaunchKernelGGL(k_flip<true>, grid, dim3(256), 0, s, a);
     else
@@ -701,10 +806,29 @@ hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
 }
 
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s) {
-    const size_t N = static_cast<size_t>(a.L) * a.L;
-    size_t blocks = (N + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_counts, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_counts, dim3(count_blocks(a.L)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace swmc
+
+namespace swmc {
+
+hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint32_t row) {
+    if (l.blocks == 0) return hipSuccess;
+    const BatchMap m{l.reps, l.map, l.begin};
+    const dim3 grid(l.blocks);
+    switch (k) {
+        case kBKBondPotts: hipLaunchKernelGGL(kb_bond_local<0>, grid, dim3(kBlock), 0, s, m); break;
+        case kBKBondClock: hipLaunchKernelGGL(kb_bond_local<1>, grid, dim3(kBlock), 0, s, m); break;
+        case kBKBlockMerge: hipLaunchKernelGGL(kb_block_merge, grid, dim3(kMergeThreads), 0, s, m); break;
+        case kBKBorderMerge: hipLaunchKernelGGL(kb_border_merge, grid, dim3(256), 0, s, m); break;
+        case kBKFlatten: hipLaunchKernelGGL(kb_flatten, grid, dim3(256), 0, s, m); break;
+        case kBKFlip: hipLaunchKernelGGL(kb_flip<false>, grid, dim3(256), 0, s, m); break;
+        case kBKFlipVerify: hipLaunchKernelGGL(kb_flip<true>, grid, dim3(256), 0, s, m); break;
+        case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(256), 0, s, m, row); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

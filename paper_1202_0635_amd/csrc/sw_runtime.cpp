@@ -10,11 +10,14 @@
 #include <vector>
 
 #include "sw.h"
+#include "sw_host.hpp"
 #include "sw_internal.hpp"
 
 using namespace swmc;
+using namespace swmc::host;
 
-namespace {
+namespace swmc {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -100,12 +103,7 @@ void build_table(const sw_lattice& p, uint32_t* out) {
 // ---------------------------------------------------------------------------
 // Device arena layout.
 // ---------------------------------------------------------------------------
-constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    size_t ctl, spins, bond_r, bond_d, labels, canon, ring, scratch_row, table, total;
-};
 
 Layout layout_of(const sw_lattice& p) {
     const size_t L = static_cast<size_t>(p.L);
@@ -125,10 +123,6 @@ Layout layout_of(const sw_lattice& p) {
     l.total = o;
     return l;
 }
-
-struct Observables {
-    double e = 0.0, m2 = 0.0;
-};
 
 Observables observables_of(const sw_lattice& p, const int64_t* row) {
     const double N = static_cast<double>(p.L) * static_cast<double>(p.L);
@@ -155,7 +149,70 @@ Observables observables_of(const sw_lattice& p, const int64_t* row) {
     return o;
 }
 
-}  // namespace
+const Control kFreshControl = {0ull, ~0ull, 0u, 1u, {}};
+
+static uint32_t div_up(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
+
+uint32_t blocks_for(int l, const SweepArgs& a) {
+    const uint64_t L = static_cast<uint64_t>(a.L);
+    const int mt = a.merge_tiles;
+    switch (l) {
+        case kLBondPotts: return a.model == SW_POTTS ? static_cast<uint32_t>(a.tiles_x * a.tiles_y) : 0u;
+        case kLBondClock: return a.model == SW_CLOCK ? static_cast<uint32_t>(a.tiles_x * a.tiles_y) : 0u;
+        case kLBlockMerge: return mt > 1 ? merge_blocks_x(a.tiles_x, mt) * merge_blocks_x(a.tiles_y, mt) : 0u;
+        case kLBorderMerge: return div_up((merge_blocks_x(a.tiles_x, mt) + merge_blocks_x(a.tiles_y, mt)) * L, 256);
+        case kLFlatten: return div_up((static_cast<uint64_t>(a.tiles_x) + a.tiles_y) * L, 256);
+        case kLFlip: return static_cast<uint32_t>(a.tiles_x * a.tiles_y);
+        case kLCounts: return count_blocks(a.L);
+        default: return 0u;
+    }
+}
+
+SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
+    SweepArgs a{};
+    a.spins = reinterpret_cast<int8_t*>(base + lay.spins);
+    a.bond_r = reinterpret_cast<uint64_t*>(base + lay.bond_r);
+    a.bond_d = reinterpret_cast<uint64_t*>(base + lay.bond_d);
+    a.labels = reinterpret_cast<uint32_t*>(base + lay.labels);
+    a.canon = reinterpret_cast<uint32_t*>(base + lay.canon);
+    a.table = reinterpret_cast<const uint32_t*>(base + lay.table);
+    a.ctl = reinterpret_cast<Control*>(base + lay.ctl);
+    a.count_row = nullptr;
+    a.L = p.L;
+    a.q = p.q;
+    a.model = p.model;
+    a.w64 = (p.L + 63) / 64;
+    a.tiles_x = (p.L + kTileW - 1) / kTileW;
+    a.tiles_y = (p.L + kTileH - 1) / kTileH;
+    a.merge_tiles = kMergeTiles;
+    a.key0 = static_cast<uint32_t>(p.seed);
+    a.key1 = static_cast<uint32_t>(p.seed >> 32);
+    return a;
+}
+
+void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, uint64_t samples, double sum_e, double sum_m2,
+              double sum_m4, sw_obs* out) {
+    std::memset(out, 0, sizeof *out);
+    out->sweeps_done = t;
+    out->samples = samples;
+    for (int k = 0; k < 32; ++k) {
+        out->hist[k] = row[k];
+        out->pair_hist[k] = row[32 + k];
+    }
+    const Observables o = observables_of(p, row);
+    out->e_per_site = o.e;
+    out->m2 = o.m2;
+    if (samples) {
+        const double n = static_cast<double>(samples);
+        out->mean_e = sum_e / n;
+        out->mean_m2 = sum_m2 / n;
+        out->mean_m4 = sum_m4 / n;
+        out->binder_u = out->mean_m2 > 0.0 ? out->mean_m4 / (out->mean_m2 * out->mean_m2) : 0.0;
+    }
+}
+
+}  // namespace host
+}  // namespace swmc
 
 struct sw_ctx {
     sw_lattice p{};
@@ -301,30 +358,15 @@ int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_c
     c->table.resize(table_entries(*p));
     build_table(*p, c->table.data());
 
+    c->args = make_args(*p, c->base, lay);
     SweepArgs& a = c->args;
-    a.spins = reinterpret_cast<int8_t*>(c->base + lay.spins);
-    a.bond_r = reinterpret_cast<uint64_t*>(c->base + lay.bond_r);
-    a.bond_d = reinterpret_cast<uint64_t*>(c->base + lay.bond_d);
-    a.labels = reinterpret_cast<uint32_t*>(c->base + lay.labels);
-    a.canon = reinterpret_cast<uint32_t*>(c->base + lay.canon);
-    a.table = reinterpret_cast<const uint32_t*>(c->base + lay.table);
-    a.ctl = reinterpret_cast<Control*>(c->base + lay.ctl);
-    a.count_row = nullptr;
-    a.L = p->L;
-    a.q = p->q;
-    a.model = p->model;
-    a.w64 = (p->L + 63) / 64;
-    a.tiles_x = (p->L + kTileW - 1) / kTileW;
-    a.tiles_y = (p->L + kTileH - 1) / kTileH;
-    a.key0 = static_cast<uint32_t>(p->seed);
-    a.key1 = static_cast<uint32_t>(p->seed >> 32);
 
     auto cleanup = [&](int st) {
         if (c->owns) (void)hipFree(c->base);
         delete c;
         return st;
     };
-    e = hipMemsetAsync(c->base + lay.ctl, 0, sizeof(Control), c->stream);
+    e = hipMemcpyAsync(c->base + lay.ctl, &kFreshControl, sizeof(Control), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->base + lay.table, c->table.data(), c->table.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_init(a, c->stream);
@@ -387,23 +429,7 @@ int sw_measure(sw_ctx* c, sw_obs* out) {
     SW_HIP(c, hipStreamSynchronize(c->stream));
     SW_HIP(c, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
     SW_HIP(c, hipMemcpy(&ctl, c->base + c->lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
-    std::memset(out, 0, sizeof *out);
-    out->sweeps_done = ctl.t;
-    out->samples = c->samples;
-    for (int k = 0; k < 32; ++k) {
-        out->hist[k] = row[k];
-        out->pair_hist[k] = row[32 + k];
-    }
-    const Observables o = observables_of(c->p, row);
-    out->e_per_site = o.e;
-    out->m2 = o.m2;
-    if (c->samples) {
-        const double n = static_cast<double>(c->samples);
-        out->mean_e = c->sum_e / n;
-        out->mean_m2 = c->sum_m2 / n;
-        out->mean_m4 = c->sum_m4 / n;
-        out->binder_u = out->mean_m2 > 0.0 ? out->mean_m4 / (out->mean_m2 * out->mean_m2) : 0.0;
-    }
+    fill_obs(c->p, row, ctl.t, c->samples, c->sum_e, c->sum_m2, c->sum_m4, out);
     return SW_OK;
 }
 
@@ -454,7 +480,7 @@ int sw_write_spins(sw_ctx* c, const int8_t* host, size_t n, uint64_t t) {
     if (!host || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
     for (size_t i = 0; i < N; ++i)
         if (host[i] < 0 || host[i] >= c->p.q) return fail(SW_EINVAL, "spin %zu = %d is not in [0, q)", i, host[i]);
-    Control ctl{};
+    Control ctl = kFreshControl;
     ctl.t = t;
     SW_HIP(c, hipStreamSynchronize(c->stream));
     SW_HIP(c, hipMemcpy(c->base + c->lay.spins, host, N, hipMemcpyHostToDevice));
@@ -496,6 +522,62 @@ int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* to
         c->prof_launches[i] = 0;
         c->prof_ms[i] = 0.0;
     }
+    return SW_OK;
+}
+
+int sw_set_schedule(sw_ctx* c, int32_t merge_tiles) {
+    const int st = check_ctx(c);
+    if (st) return st;
+    if (merge_tiles != 1 && merge_tiles != 2 && merge_tiles != 4 && merge_tiles != 8)
+        return fail(SW_EINVAL, "merge_tiles must be 1, 2, 4 or 8");
+    c->args.merge_tiles = merge_tiles;
+    return SW_OK;
+}
+
+int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles) {
+    int st = check_ctx(c);
+    if (st) return st;
+    if (sweeps <= 0 || !merge_tiles) return fail(SW_EINVAL, "need sweeps > 0 and an output pointer");
+    const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
+    void* tmp = nullptr;
+    SW_HIP(c, hipMalloc(&tmp, up(N) + up(sizeof(Control))));
+    char* spins = c->base + c->lay.spins;
+    char* ctl = c->base + c->lay.ctl;
+    char* s_spins = static_cast<char*>(tmp);
+    char* s_ctl = s_spins + up(N);
+    hipError_t e = hipMemcpyAsync(s_spins, spins, N, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s_ctl, ctl, sizeof(Control), hipMemcpyDeviceToDevice, c->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = c->args.merge_tiles;
+    float best_ms = 0.0f;
+    for (int mt : {1, 2, 4, 8}) {
+        if (e != hipSuccess || st) break;
+        c->args.merge_tiles = mt;
+        st = sw_sweep(c, 1, 0);
+        if (!st) e = hipEventRecord(e0, c->stream);
+        if (!st && e == hipSuccess) st = sw_sweep(c, sweeps, 0);
+        if (!st && e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (!st && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (!st && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (!st && e == hipSuccess && (best_ms == 0.0f || ms < best_ms)) {
+            best_ms = ms;
+            best = mt;
+        }
+        if (!st && e == hipSuccess) e = hipMemcpyAsync(spins, s_spins, N, hipMemcpyDeviceToDevice, c->stream);
+        if (!st && e == hipSuccess) e = hipMemcpyAsync(ctl, s_ctl, sizeof(Control), hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e == hipSuccess && !st) e = hipStreamSynchronize(c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(tmp);
+    if (st) return st;
+    if (e != hipSuccess) return device_fail(c, e, "sw_tune");
+    c->args.merge_tiles = best;
+    c->have_canon = false;
+    *merge_tiles = best;
     return SW_OK;
 }
 

@@ -1,0 +1,125 @@
+"""GPU: schedules, the autotuner and batches keep the chain bit-identical.
+
+Canonical labels are unique, so the merge schedule cannot change any result;
+a batch replica must follow exactly the chain of the same lattice swept alone
+(and so the oracle's)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TC2 = 1.0 / math.log(1.0 + math.sqrt(2.0))
+TC3 = 1.0 / math.log(1.0 + math.sqrt(3.0))
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def swmc():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    import paper_1202_0635_amd as swmc
+
+    swmc._lib.lib()
+    return swmc
+
+
+@pytest.mark.parametrize("mt", [1, 2, 4, 8])
+def test_schedule_does_not_change_results(swmc, orc, mt):
+    L, q = 300, 2
+    _say(f"[schedule] L={L} merge_tiles={mt}")
+    lat = swmc.Lattice(L, q, "potts", T=TC2, seed=41).set_schedule(mt)
+    ch = orc.Chain(L, q, "potts", T=TC2, seed=41)
+    for _ in range(3):
+        lat.sweep(1, verify=True)
+        ch.sweep(1)
+        assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+        assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+
+
+def test_tune_leaves_the_chain_unchanged(swmc, orc):
+    L = 200
+    _say("[tune] lattice")
+    lat = swmc.Lattice(L, 3, "potts", T=TC3, seed=5)
+    lat.sweep(4)
+    chosen = lat.tune(3)
+    assert chosen in (1, 2, 4, 8)
+    lat.sweep(2, verify=True)
+    ch = orc.Chain(L, 3, "potts", T=TC3, seed=5).sweep(6)
+    assert lat.measure()["t"] == 6
+    assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+    assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+
+
+MIX = [
+    (64, 2, "potts", TC2, 1.0, 1),
+    (100, 3, "potts", TC3, 1.0, 7),
+    (130, 6, "clock", 0.9, 1.0, 3),
+    (2, 2, "potts", TC2, 1.0, 5),
+    (257, 4, "potts", 0.9, 1.0, 9),
+    (65, 2, "clock", 1.2, 1.0, 12),
+    (33, 32, "potts", 0.4, 1.0, 15),
+    (128, 3, "potts", 1.1, 0.8, 0x4000),
+]
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_replicas_follow_their_own_chains(swmc, orc, graph):
+    _say(f"[batch] mix graph={graph}")
+    b = swmc.Batch(MIX)
+    b.sweep(4, graph=graph)
+    b.sweep(1, verify=True, graph=graph)
+    for r, (L, q, model, T, J, seed) in enumerate(MIX):
+        ch = orc.Chain(L, q, model, T=T, J=J, seed=seed).sweep(5)
+        assert np.array_equal(b.spins(r).reshape(-1), ch.spins), f"replica {r} spins"
+        assert np.array_equal(b.labels(r).reshape(-1), ch.labels), f"replica {r} labels"
+        assert b.measure(r)["t"] == 5
+    b.close()
+
+
+def test_batch_equals_alone_and_measures(swmc, orc):
+    specs = [(96, 3, "potts", TC3 * (0.9 + 0.2 * r / 7), 1.0, 0x4000 + r) for r in range(8)]
+    _say("[batch] measure")
+    b = swmc.Batch(specs)
+    b.sweep(10)
+    b.sweep(20, measure=True)
+    for r, (L, q, model, T, J, seed) in enumerate(specs):
+        lat = swmc.Lattice(L, q, model, T=T, J=J, seed=seed)
+        lat.sweep(10)
+        lat.sweep(20, measure=True)
+        ob, ol = b.measure(r), lat.measure()
+        assert np.array_equal(b.spins(r), lat.spins())
+        for k in ("t", "samples"):
+            assert ob[k] == ol[k]
+        assert np.array_equal(ob["hist"], ol["hist"]) and np.array_equal(ob["pair_hist"], ol["pair_hist"])
+        for k in ("mean_e", "mean_m2", "mean_m4", "binder_u"):
+            assert ob[k] == ol[k]
+        lat.close()
+    b.close()
+
+
+def test_batch_schedules_and_tune(swmc, orc):
+    specs = [(L, 3, "potts", TC3, 1.0, 100 + i) for i, L in enumerate((64, 128, 256, 512, 300, 70))]
+    _say("[batch] schedules")
+    ref = swmc.Batch(specs)
+    ref.sweep(6)
+    for mt in (1, 2, 8):
+        b = swmc.Batch(specs).set_schedule(mt)
+        b.sweep(6)
+        for r in range(len(specs)):
+            assert np.array_equal(b.spins(r), ref.spins(r)), (mt, r)
+        b.close()
+    b = swmc.Batch(specs)
+    b.sweep(3)
+    assert b.tune(2) in (1, 2, 4, 8)
+    b.sweep(3)
+    for r in range(len(specs)):
+        assert np.array_equal(b.spins(r), ref.spins(r))
+        assert b.measure(r)["t"] == 6
