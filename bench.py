@@ -162,11 +162,15 @@ def bench_serve(args) -> dict:
 
     trace = request_trace(args.requests)
     budget = int(args.budget_gib * (1 << 30))
+    note = lambda msg: print(f"[serve] {msg}", file=sys.stderr, flush=True)
     sat = serve.run_trace(trace, serve.poisson_arrivals(len(trace), 0.0), budget, args.slots, args.sweeps_per_step)
     capacity = len(trace) / sat["makespan_s"]
+    note(f"saturation run done: {sat['makespan_s']:.2f} s, capacity {capacity:.1f} requests/s")
     arrivals = serve.poisson_arrivals(len(trace), 0.8 * capacity, seed=20120203)
     served = serve.run_trace(trace, arrivals, budget, args.slots, args.sweeps_per_step)
+    note(f"served run done: {served['makespan_s']:.2f} s")
     plain = serve.run_plain(trace, arrivals)
+    note(f"plain run done: {plain['makespan_s']:.2f} s")
     same = all(served["results"][i]["spin_hash"] == plain["results"][i]["spin_hash"] for i in range(len(trace)))
     strip = lambda d: {k: v for k, v in d.items() if k not in ("results", "stats")}
     return {"metric": "served vs plain throughput (SW requests, continuous batching)",
@@ -231,10 +235,21 @@ def main() -> int:
     ms = e0.elapsed_time(e1)
     ns_per_update = ms * 1e6 / (args.steps * N)
 
-    # Per-kernel launch times over a second pass of the same number of sweeps.
+    # The same number of sweeps with the per-sweep counts (update + measurement).
+    e0.record(stream)
+    lat.sweep(args.steps, measure=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_measure = e0.elapsed_time(e1)
+
+    # Per-kernel launch times over further passes of the same number of sweeps
+    # (the second with the per-sweep counts, for the count kernel's time).
     lat.sweep(args.steps, profile=True)
     prof = lat.profile()
     kernels = {k: {"launches": n, "avg_us": 1e3 * t / n} for k, (n, t) in prof.items() if n}
+    lat.sweep(args.steps, measure=True, profile=True)
+    n_c, t_c = lat.profile().get("k_counts", (0, 0.0))
+    count_us = 1e3 * t_c / n_c if n_c else None
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     dom_bytes = alg_bytes_per_launch(dom, cfg.L, cfg.model)
     achieved = dom_bytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
@@ -259,6 +274,8 @@ def main() -> int:
                    "seed": cfg.seed, "warmup_sweeps": args.warmup, "timed_sweeps": args.steps,
                    "merge_tiles": schedule},
         "spin_updates_per_s": N * args.steps / (ms * 1e-3),
+        "ns_per_update_with_measurement": ms_measure * 1e6 / (args.steps * N),
+        "k_counts_avg_us": count_us,
         "sweep_alg_GBps": sweep_gbps,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -137,9 +137,10 @@ int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n);
 int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* total_ms,
                     int32_t cap, int32_t* nk);
 
-/* Schedule: tiles per side of the blocks whose inner borders the first merge
- * level joins (1 = single-level merge; 1, 2, 4 or 8).  Results do not depend on
- * it (canonical labels are unique); only the time does. */
+/* Merge schedule: 1 = one device-wide border kernel; 2 or 4 (default 4) = the
+ * inner borders of blocks of that many tiles per side are first joined inside
+ * one workgroup, in LDS.  Other values: SW_EINVAL.  Results do not depend on it
+ * (canonical labels are unique); only the time does. */
 int sw_set_schedule(sw_ctx* c, int32_t merge_tiles);
 /* Autotuner: times `sweeps` sweeps under every schedule from the current state,
  * restores the state (spins and sweep index) after each, keeps the fastest and

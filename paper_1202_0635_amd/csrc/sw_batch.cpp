@@ -21,7 +21,7 @@ using namespace swmc::host;
 
 namespace {
 
-constexpr int kSchedules[] = {1, 2, 4, 8};  // first-level merge block sizes the tuner tries
+constexpr int kSchedules[] = {1, 2, 4};  // first-level merge block sizes the tuner tries
 
 constexpr BatchKernel kListKernel[kNumLists] = {kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge,
                                                 kBKFlatten,   kBKFlip,      kBKCounts};
@@ -352,7 +352,7 @@ int sw_batch_set_schedule(sw_batch* b, int32_t merge_tiles) {
     if (st) return st;
     bool ok = false;
     for (int mt : kSchedules) ok = ok || (mt == merge_tiles);
-    if (!ok) return fail(SW_EINVAL, "merge_tiles must be 1, 2, 4 or 8");
+    if (!ok) return fail(SW_EINVAL, "merge_tiles must be 1, 2 or 4");
     if (merge_tiles == b->merge_tiles) return SW_OK;
     b->merge_tiles = merge_tiles;
     return upload_lists(b);

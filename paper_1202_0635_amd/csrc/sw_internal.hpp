@@ -14,8 +14,9 @@ constexpr int kTileW = 64;
 constexpr int kTileH = 64;
 constexpr int kWaves = 4;
 constexpr int kBlock = kWaves * 64;
-// Default tiles per side of the blocks whose inner borders the first merge
-// level joins (a per-context schedule parameter, see the autotuner).
+// Merge schedule (a per-context parameter, see the autotuner): 1 runs one
+// device-wide border kernel; 2 or 4 first join the inner borders of blocks of
+// that many tiles per side inside one workgroup (in LDS).
 constexpr int kMergeTiles = 4;
 // Threads of a first-level merge workgroup.
 constexpr int kMergeThreads = 1024;
@@ -75,7 +76,9 @@ __host__ __device__ inline uint32_t count_blocks(int L) {
     const uint64_t n = (static_cast<uint64_t>(L) * L + 255) / 256;
     return static_cast<uint32_t>(n < 1024 ? n : 1024);
 }
-__host__ __device__ inline uint32_t merge_blocks_x(int tiles_x, int mt) { return static_cast<uint32_t>((tiles_x + mt - 1) / mt); }
+__host__ __device__ inline uint32_t merge_blocks_x(int tiles_x, int mt) {
+    return mt > 0 ? static_cast<uint32_t>((tiles_x + mt - 1) / mt) : 0u;
+}
 
 // Batched launches: one launch covers the workgroups of every replica.
 enum BatchKernel {

@@ -147,17 +147,54 @@ __device__ __forceinline__ int mirror_of(uint64_t t, int q, uint32_t k0, uint32_
 }
 
 __device__ __forceinline__ uint32_t bond_bit(const uint64_t* bonds, int w64, int x, int y) {
-    return static_cast<uint32_t>(bonds[static_cast<size_t>(y) * w64 + (x >> 6)] >> (x & 63)) & 1u;
+    return static_cast<uint32_t>(bonds[__umul24(y, w64) + (static_cast<uint32_t>(x) >> 6)] >> (x & 63)) & 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Bonds that leave a tile (or wrap around the torus).  A bond is skipped
+// when the neighbouring bond along the same border joins the same two
+// tile-local sets (both its ends are tile-internal neighbours).
+// ---------------------------------------------------------------------------
+struct BorderBond {
+    bool active;
+    uint32_t i, j;
+};
+
+// Right-edge bond of tile column tx in row y (wrapping to column 0 after the
+// last column).  Skipped when row y-1 of the same tile row already joins the
+// same two tile-local sets: both of its ends are tile-internal neighbours.
+__device__ __forceinline__ BorderBond vertical_border_bond(const SweepArgs& a, int tx, int y) {
+    const int L = a.L;
+    const int xe = min((tx + 1) * kTileW, L) - 1;
+    const int xr = (xe + 1 == L) ? 0 : xe + 1;
+    if (!bond_bit(a.bond_r, a.w64, xe, y)) return {false, 0u, 0u};
+    if ((y % kTileH) != 0 && bond_bit(a.bond_r, a.w64, xe, y - 1) && bond_bit(a.bond_d, a.w64, xe, y - 1) &&
+        bond_bit(a.bond_d, a.w64, xr, y - 1))
+        return {false, 0u, 0u};
+    const uint32_t row = __umul24(y, L);
+    return {true, row + static_cast<uint32_t>(xe), row + static_cast<uint32_t>(xr)};
+}
+
+// Bottom-edge bond of tile row ty in column x (wrapping to row 0).
+__device__ __forceinline__ BorderBond horizontal_border_bond(const SweepArgs& a, int ty, int x) {
+    const int L = a.L;
+    const int ye = min((ty + 1) * kTileH, L) - 1;
+    const int yd = (ye + 1 == L) ? 0 : ye + 1;
+    if (!bond_bit(a.bond_d, a.w64, x, ye)) return {false, 0u, 0u};
+    if ((x % kTileW) != 0 && bond_bit(a.bond_d, a.w64, x - 1, ye) && bond_bit(a.bond_r, a.w64, x - 1, ye) &&
+        bond_bit(a.bond_r, a.w64, x - 1, yd))
+        return {false, 0u, 0u};
+    return {true, __umul24(ye, L) + static_cast<uint32_t>(x), __umul24(yd, L) + static_cast<uint32_t>(x)};
 }
 
 // ---------------------------------------------------------------------------
 // Random start: s_i = qmap(draw(i, 0, init)).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_init(SweepArgs a) {
-    const size_t N = static_cast<size_t>(a.L) * a.L;
-    const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t N = __umul24(a.L, a.L);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const Words4 w = draw(static_cast<uint32_t>(i), 0, kInit, a.key0, a.key1);
+    const Words4 w = draw(i, 0, kInit, a.key0, a.key1);
     a.spins[i] = static_cast<int8_t>(qmap(w.w0, static_cast<uint32_t>(a.q)));
 }
 
@@ -188,6 +225,9 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     const int L = a.L, q = a.q;
     const int x0 = tx * kTileW, y0 = ty * kTileH;
     const int x = x0 + lane;
+    // Site indices stay below 2^31 (L <= 46340), so 32-bit arithmetic with
+    // 24-bit multiplies (L < 2^16) replaces 64-bit address products.
+    const uint32_t tile_base = __umul24(y0, L) + static_cast<uint32_t>(x0);
     const bool col_ok = x < L;
     const int nvalid = min(kTileW, L - x0);
     // lanes whose right bond stays inside the tile (not the last column, no wrap)
@@ -213,7 +253,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     if (threadIdx.x < kTileH) {
         const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
         const int yh = y0 + static_cast<int>(threadIdx.x);
-        halo[threadIdx.x] = (yh < L) ? a.spins[static_cast<size_t>(yh) * L + xh] : 0;
+        halo[threadIdx.x] = (yh < L) ? a.spins[__umul24(yh, L) + static_cast<uint32_t>(xh)] : 0;
     }
     __syncthreads();
 
@@ -223,7 +263,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
 #pragma unroll
     for (int r = 0; r <= RPW; ++r) {
         const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
-        sreg[r] = (col_ok && yr <= L) ? a.spins[static_cast<size_t>(yr == L ? 0 : yr) * L + x] : 0;
+        sreg[r] = (col_ok && yr <= L) ? a.spins[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : 0;
     }
     const bool edge_lane = (lane == nvalid - 1);
 
@@ -233,7 +273,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const int ly0 = ly_base + g * 8;
         const int yb = y0 + ly0;  // multiple of 8
         Words4 hi = {0, 0, 0, 0};
-        if (col_ok && yb < L) hi = draw(static_cast<uint32_t>((yb >> 3) * L + x), t, kBondHi, k0, k1);
+        if (col_ok && yb < L) hi = draw(__umul24(yb >> 3, L) + static_cast<uint32_t>(x), t, kBondHi, k0, k1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int r = g * 8 + k;
@@ -278,16 +318,17 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t e = P[j];
         const int ly = static_cast<int>((e & 0xFFFu) >> 6), lx = static_cast<int>(e & 63u);
         const int y = y0 + ly, xx = x0 + lx;
-        const size_t i = static_cast<size_t>(y) * L + xx;
-        const Words4 lo = draw(static_cast<uint32_t>(i), t, kBondLo, k0, k1);
+        const uint32_t row = __umul24(y, L);
+        const uint32_t i = row + static_cast<uint32_t>(xx);
+        const Words4 lo = draw(i, t, kBondLo, k0, k1);
         const int s = a.spins[i];
         if (e & (1u << 12)) {
-            const int sr = a.spins[static_cast<size_t>(y) * L + ((xx + 1 == L) ? 0 : xx + 1)];
+            const int sr = a.spins[row + static_cast<uint32_t>((xx + 1 == L) ? 0 : xx + 1)];
             const uint32_t c = kClock ? cut[s * q + sr] : c_eq;  // a Potts tie implies equal spins
             if ((lo.w0 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_r[ly], 1ull << lx);
         }
         if (e & (1u << 13)) {
-            const int sd = a.spins[static_cast<size_t>((y + 1 == L) ? 0 : y + 1) * L + xx];
+            const int sd = a.spins[__umul24((y + 1 == L) ? 0 : y + 1, L) + static_cast<uint32_t>(xx)];
             const uint32_t c = kClock ? cut[s * q + sd] : c_eq;
             if ((lo.w1 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_d[ly], 1ull << lx);
         }
@@ -299,10 +340,11 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const int ly = threadIdx.x & (kTileH - 1);
         const int y = y0 + ly;
         if (y < L) {
+            const uint32_t wi = __umul24(y, a.w64) + static_cast<uint32_t>(tx);
             if (threadIdx.x < kTileH)
-                a.bond_r[static_cast<size_t>(y) * a.w64 + tx] = raw_r[ly];
+                a.bond_r[wi] = raw_r[ly];
             else
-                a.bond_d[static_cast<size_t>(y) * a.w64 + tx] = raw_d[ly];
+                a.bond_d[wi] = raw_d[ly];
         }
     }
     // Phase 2: each wave labels its strip of rows in raster order, as the
@@ -380,13 +422,10 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const bool is_root = ok && (root == self);
         // every site of the row is stored (a root gets a placeholder root word
         // that its draw below overwrites), so label lines are written whole
-        if (ok)
-            a.labels[static_cast<size_t>(y) * L + x] =
-                is_root ? kRootFlag
-                        : static_cast<uint32_t>((y0 + static_cast<int>(root >> 6)) * L + x0 + static_cast<int>(root & 63));
+        const uint32_t i = __umul24(y, L) + static_cast<uint32_t>(x);
+        if (ok) a.labels[i] = is_root ? kRootFlag : tile_base + __umul24(root >> 6, L) + (root & 63u);
         const uint64_t rm = __ballot(is_root);
-        if (is_root)
-            list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] = static_cast<uint32_t>(y * L + x);
+        if (is_root) list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] = i;
         nroots += static_cast<uint32_t>(__popcll(rm));
     }
     __syncthreads();
@@ -400,107 +439,99 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
 }
 
-// ---------------------------------------------------------------------------
-// Bonds that leave a tile (or wrap around the torus).  Thread g < nv: right
-// edge of tile column g / L, row g % L; otherwise bottom edge of a tile row.
-// The bond is skipped when the neighbouring bond along the same border joins
-// the same two tile-local sets (both its ends are tile-internal neighbours).
-// ---------------------------------------------------------------------------
-struct BorderBond {
-    bool active;
-    uint32_t i, j;
-};
-
-// Right-edge bond of tile column tx in row y (wrapping to column 0 after the
-// last column).  Skipped when row y-1 of the same tile row already joins the
-// same two tile-local sets: both of its ends are tile-internal neighbours.
-__device__ __forceinline__ BorderBond vertical_border_bond(const SweepArgs& a, int tx, int y) {
-    const int L = a.L;
-    const int xe = min((tx + 1) * kTileW, L) - 1;
-    const int xr = (xe + 1 == L) ? 0 : xe + 1;
-    if (!bond_bit(a.bond_r, a.w64, xe, y)) return {false, 0u, 0u};
-    if ((y % kTileH) != 0 && bond_bit(a.bond_r, a.w64, xe, y - 1) && bond_bit(a.bond_d, a.w64, xe, y - 1) &&
-        bond_bit(a.bond_d, a.w64, xr, y - 1))
-        return {false, 0u, 0u};
-    return {true, static_cast<uint32_t>(y * L + xe), static_cast<uint32_t>(y * L + xr)};
-}
-
-// Bottom-edge bond of tile row ty in column x (wrapping to row 0).
-__device__ __forceinline__ BorderBond horizontal_border_bond(const SweepArgs& a, int ty, int x) {
-    const int L = a.L;
-    const int ye = min((ty + 1) * kTileH, L) - 1;
-    const int yd = (ye + 1 == L) ? 0 : ye + 1;
-    if (!bond_bit(a.bond_d, a.w64, x, ye)) return {false, 0u, 0u};
-    if ((x % kTileW) != 0 && bond_bit(a.bond_d, a.w64, x - 1, ye) && bond_bit(a.bond_r, a.w64, x - 1, ye) &&
-        bond_bit(a.bond_r, a.w64, x - 1, yd))
-        return {false, 0u, 0u};
-    return {true, static_cast<uint32_t>(ye * L + x), static_cast<uint32_t>(yd * L + x)};
-}
-
-// Thread g of a launch over every tile border: g < tiles_x*L is a vertical
-// border position, the rest horizontal.
-__device__ __forceinline__ BorderBond border_bond(const SweepArgs& a, size_t gid) {
-    const int L = a.L;
-    const size_t nv = static_cast<size_t>(a.tiles_x) * L;
-    const size_t nh = static_cast<size_t>(a.tiles_y) * L;
-    if (gid < nv) return vertical_border_bond(a, static_cast<int>(gid / L), static_cast<int>(gid % L));
-    if (gid < nv + nh) {
-        const size_t h = gid - nv;
-        return horizontal_border_bond(a, static_cast<int>(h / L), static_cast<int>(h % L));
+// Thread g of a launch over the bonds that cross every step-th tile border
+// (the right edge of tile columns step-1, 2 step-1, ... and the last column;
+// likewise for tile rows).  g < nvb * L is row g % L of vertical border
+// g / L; the rest is column h % L of horizontal border h / L.  Neighbouring
+// threads take neighbouring sites of one border, which mostly share their
+// tile-local roots, so their finds meet in the same cache lines.
+__device__ __forceinline__ BorderBond border_bond(const SweepArgs& a, uint32_t g, const int step) {
+    const uint32_t L = static_cast<uint32_t>(a.L);
+    const uint32_t nvb = static_cast<uint32_t>((a.tiles_x + step - 1) / step);
+    const uint32_t nhb = static_cast<uint32_t>((a.tiles_y + step - 1) / step);
+    if (g < nvb * L) {
+        const uint32_t k = g / L, y = g - k * L;
+        return vertical_border_bond(a, min(static_cast<int>(k) * step + step - 1, a.tiles_x - 1), static_cast<int>(y));
+    }
+    g -= nvb * L;
+    if (g < nhb * L) {
+        const uint32_t r = g / L, x = g - r * L;
+        return horizontal_border_bond(a, min(static_cast<int>(r) * step + step - 1, a.tiles_y - 1), static_cast<int>(x));
     }
     return {false, 0u, 0u};
 }
 
 // ---------------------------------------------------------------------------
-// Merge, level 1: one workgroup per block of kMergeTiles x kMergeTiles tiles
-// joins the block's internal tile borders.  The forest nodes it visits (the
-// block's sites and tile-local roots) belong to no other workgroup during
-// this kernel, so workgroup-scope atomics and cached loads suffice.
+// Merge, level 1: one workgroup per block of mt x mt tiles (mt <= 4) joins
+// the block's inner tile borders in LDS.  The ends of every active inner
+// border bond are mapped to their tile-local roots (one load each: a site's
+// label word names its tile-local root), the roots are entered in an LDS
+// hash table (slot = node), and the unions run on an LDS forest whose links
+// always go from the larger site index to the smaller.  Finally every node
+// that is no longer a root has its global root word replaced by a link to
+// its block root.  The nodes belong to this block only, so nothing here
+// races with another workgroup.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wg_load(const uint32_t* p) {
-    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+constexpr uint32_t kHashSlots = 8192;   // >= 2x the most nodes: 2 ends x 2 (mt-1) mt 64 bonds at mt = 4
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+static_assert(kHashSlots >= 2u * 2u * 2u * 3u * 4u * 64u, "hash table sized for 4 x 4 tile blocks");
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key) { return (key * 2654435761u) >> 19; }  // 13 bits
+
+// Slot of key in the table, inserting it if absent (linear probing; the
+// table is never more than 3/8 full, so a free slot is always reached).
+__device__ __forceinline__ uint32_t hash_insert(uint32_t* keys, uint32_t key) {
+    uint32_t s = hash_slot(key);
+    for (uint32_t n = 0; n < kHashSlots; ++n) {
+        const uint32_t old = atomicCAS(&keys[s], kEmptyKey, key);
+        if (old == kEmptyKey || old == key) return s;
+        s = (s + 1) & (kHashSlots - 1);
+    }
+    return kHashSlots;  // unreachable by the sizing above
 }
 
-__device__ __forceinline__ uint32_t wg_find(uint32_t* lab, uint32_t x, uint32_t* word) {
-    uint32_t w = wg_load(&lab[x]);
-    while (!(w & kRootFlag)) {
-        const uint32_t w2 = wg_load(&lab[w]);
-        if (w2 & kRootFlag) {
-            *word = w2;
-            return w;
-        }
-        __hip_atomic_store(&lab[x], w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        x = w2;
-        w = wg_load(&lab[x]);
+__device__ __forceinline__ uint32_t node_find(uint32_t* par, uint32_t x) {
+    uint32_t p = lds_load(&par[x]);
+    while (p != x) {
+        const uint32_t gp = lds_load(&par[p]);
+        if (gp == p) return p;
+        lds_store(&par[x], gp);
+        x = gp;
+        p = lds_load(&par[x]);
     }
-    *word = w;
     return x;
 }
 
-__device__ void wg_union(uint32_t* lab, uint32_t a, uint32_t b) {
-    uint32_t wa, wb;
-    a = wg_find(lab, a, &wa);
-    b = wg_find(lab, b, &wb);
-    while (a != b) {
-        if (a > b) {
-            uint32_t tmp = a;
+// Join the sets of nodes a and b: the root with the larger key (site index)
+// is linked under the other by compare-and-swap; a lost race retries.
+__device__ __forceinline__ void node_union(uint32_t* par, const uint32_t* keys, uint32_t a, uint32_t b) {
+    while (true) {
+        a = node_find(par, a);
+        b = node_find(par, b);
+        if (a == b) return;
+        if (keys[a] > keys[b]) {
+            const uint32_t tmp = a;
             a = b;
             b = tmp;
-            tmp = wa;
-            wa = wb;
-            wb = tmp;
         }
-        uint32_t expected = wb;
-        if (__hip_atomic_compare_exchange_strong(&lab[b], &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-        b = wg_find(lab, b, &wb);
-        a = wg_find(lab, a, &wa);
+        if (atomicCAS(&par[b], b, a) == b) return;
     }
 }
 
+__device__ __forceinline__ uint32_t tile_root(const uint32_t* lab, uint32_t i) {
+    const uint32_t w = lab[i];
+    return (w & kRootFlag) ? i : w;
+}
+
 __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, const int by) {
+    __shared__ uint32_t keys[kHashSlots];
+    __shared__ uint32_t par[kHashSlots];
     if (!a.ctl->live) return;
+    for (uint32_t k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
+        keys[k] = kEmptyKey;
+        par[k] = k;
+    }
+    __syncthreads();
     const int L = a.L;
     const int mt = a.merge_tiles;
     const int txa = bx * mt, tya = by * mt;
@@ -510,13 +541,34 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
     const int ncols = min((txa + ntx) * kTileW, L) - xa;
     const int nv = (ntx - 1) * nrows;  // bonds across the block's inner vertical tile borders
     const int nh = (nty - 1) * ncols;
-    for (int k = threadIdx.x; k < nv + nh; k += blockDim.x) {
+    // at most 2 (mt-1) mt 64 <= 1536 bonds: two per thread of a 1024-thread workgroup
+    constexpr int kPer = 2;
+    static_assert(kPer * kMergeThreads >= 2 * 3 * 4 * 64, "bonds per thread");
+    uint32_t ends[kPer][2];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int k = static_cast<int>(threadIdx.x) + r * kMergeThreads;
+        ends[r][0] = ends[r][1] = kHashSlots;
+        if (k >= nv + nh) continue;
         BorderBond b;
         if (k < nv)
             b = vertical_border_bond(a, txa + k / nrows, ya + k % nrows);
         else
             b = horizontal_border_bond(a, tya + (k - nv) / ncols, xa + (k - nv) % ncols);
-        if (b.active) wg_union(a.labels, b.i, b.j);
+        if (!b.active) continue;
+        ends[r][0] = hash_insert(keys, tile_root(a.labels, b.i));
+        ends[r][1] = hash_insert(keys, tile_root(a.labels, b.j));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+        if (ends[r][0] < kHashSlots && ends[r][1] < kHashSlots) node_union(par, keys, ends[r][0], ends[r][1]);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
+        const uint32_t key = keys[k];
+        if (key == kEmptyKey) continue;
+        const uint32_t r = node_find(par, k);
+        if (r != k) a.labels[key] = keys[r];
     }
 }
 
@@ -525,22 +577,9 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
 // device-wide lock-free union.  Thread g < nbx*L: right edge of the last tile
 // column of block column g / L; the rest: bottom edges of block rows.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void border_merge(const SweepArgs& a, const size_t gid) {
+__device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t gid) {
     if (!a.ctl->live) return;
-    const int L = a.L;
-    const int mt = a.merge_tiles;
-    const int nbx = (a.tiles_x + mt - 1) / mt;
-    const int nby = (a.tiles_y + mt - 1) / mt;
-    const size_t nv = static_cast<size_t>(nbx) * L;
-    BorderBond b{false, 0u, 0u};
-    if (gid < nv) {
-        const int bx = static_cast<int>(gid / L);
-        b = vertical_border_bond(a, min(bx * mt + mt - 1, a.tiles_x - 1), static_cast<int>(gid % L));
-    } else if (gid < nv + static_cast<size_t>(nby) * L) {
-        const size_t h = gid - nv;
-        const int by = static_cast<int>(h / L);
-        b = horizontal_border_bond(a, min(by * mt + mt - 1, a.tiles_y - 1), static_cast<int>(h % L));
-    }
+    const BorderBond b = border_bond(a, gid, a.merge_tiles);
     if (b.active) g_union(a.labels, b.i, b.j);
 }
 
@@ -575,7 +614,7 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
     // Every kernel that reads the sweep index has finished (stream order); the
     // flip only needs the mirror recorded by k_bond_local.
     if (block == 0 && threadIdx.x == 0) a.ctl->t += 1;
-    const BorderBond b = border_bond(a, static_cast<size_t>(block) * blockDim.x + threadIdx.x);
+    const BorderBond b = border_bond(a, block * blockDim.x + threadIdx.x, 1);
     if (!b.active) return;
     flatten_from(a.labels, b.i);
     flatten_from(a.labels, b.j);
@@ -595,8 +634,8 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
     const int xs = tx * kTileW + static_cast<int>(threadIdx.x & 3) * 16;
     if (y >= L || xs >= L) return;
     const int nx = min(16, L - xs);
-    const size_t base = static_cast<size_t>(y) * L + xs;
-    const bool full = (nx == 16) && ((base & 3) == 0);
+    const uint32_t base = __umul24(y, L) + static_cast<uint32_t>(xs);
+    const bool full = (nx == 16) && ((base & 3u) == 0);
     uint32_t x[16], w[16];
     if (full) {
 #pragma unroll
@@ -609,7 +648,7 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
         for (int k = 0; k < 16; ++k) w[k] = (k < nx) ? a.labels[base + k] : kRootFlag;
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = static_cast<uint32_t>(base + k);
+    for (int k = 0; k < 16; ++k) x[k] = base + k;
     // follow the sixteen paths together (independent loads in flight)
     bool pending = true;
     while (pending) {
@@ -658,51 +697,120 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
 
 // ---------------------------------------------------------------------------
 // Integer counts of the current state: n[k] and the owned-bond histogram of
-// (s_j - s_i) mod q, accumulated into one int64 row.
+// (s_j - s_i) mod q, accumulated into one int64 row.  Workgroup b takes rows
+// b, b + nblocks, ...; thread t takes four consecutive sites per step (one
+// 4-byte load of the row and one of the row below, the right neighbour of
+// the fourth site from the next thread), and the steps of a row are
+// unrolled so that their loads are in flight together.  For q <= kBallotQ
+// the counts are wave ballots summed in scalar registers; larger q uses LDS
+// atomics.  One global atomic per bin and workgroup.
 // ---------------------------------------------------------------------------
+constexpr int kBallotQ = 8;
+
+__device__ __forceinline__ void count_site(int s, int sr, int sd, bool ok, int q, bool by_ballot, uint32_t* cn,
+                                           uint32_t* cp, uint32_t* h) {
+    int dr = sr - s, dd = sd - s;
+    if (dr < 0) dr += q;
+    if (dd < 0) dd += q;
+    if (by_ballot) {
+#pragma unroll
+        for (int k = 0; k < kBallotQ; ++k)
+            if (k < q) {
+                cn[k] += static_cast<uint32_t>(__popcll(__ballot(ok && s == k)));
+                cp[k] += static_cast<uint32_t>(__popcll(__ballot(ok && dr == k)) + __popcll(__ballot(ok && dd == k)));
+            }
+    } else if (ok) {
+        atomicAdd(&h[s], 1u);
+        atomicAdd(&h[32 + dr], 1u);
+        atomicAdd(&h[32 + dd], 1u);
+    }
+}
+
 __device__ __forceinline__ void counts(const SweepArgs& a, int64_t* row, const uint32_t block, const uint32_t nblocks) {
     __shared__ uint32_t h[kRowWords];
     for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) h[k] = 0;
     __syncthreads();
     const int L = a.L, q = a.q;
-    const size_t N = static_cast<size_t>(L) * L;
-    for (size_t i = static_cast<size_t>(block) * blockDim.x + threadIdx.x; i < N;
-         i += static_cast<size_t>(nblocks) * blockDim.x) {
-        const int y = static_cast<int>(i / L), x = static_cast<int>(i % L);
-        const int s = a.spins[i];
-        const int sr = a.spins[static_cast<size_t>(y) * L + ((x + 1 == L) ? 0 : x + 1)];
-        const int sd = a.spins[static_cast<size_t>((y + 1 == L) ? 0 : y + 1) * L + x];
-        int dr = sr - s, dd = sd - s;
-        if (dr < 0) dr += q;
-        if (dd < 0) dd += q;
-        atomicAdd(&h[s], 1u);
-        atomicAdd(&h[32 + dr], 1u);
-        atomicAdd(&h[32 + dd], 1u);
+    const bool by_ballot = q <= kBallotQ;
+    const bool aligned = (L & 3) == 0;
+    uint32_t cn[kBallotQ] = {}, cp[kBallotQ] = {};
+    const int span = 4 * static_cast<int>(blockDim.x);
+    for (int y = static_cast<int>(block); y < L; y += static_cast<int>(nblocks)) {
+        const uint32_t here = __umul24(y, L);
+        const uint32_t below = __umul24((y + 1 == L) ? 0 : y + 1, L);
+#pragma unroll 4
+        for (int x0 = 0; x0 < L; x0 += span) {
+            const int x = x0 + 4 * static_cast<int>(threadIdx.x);
+            int s[5] = {0, 0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
+            if (aligned && x + 4 <= L) {
+                const uint32_t w = *reinterpret_cast<const uint32_t*>(a.spins + here + x);
+                const uint32_t v = *reinterpret_cast<const uint32_t*>(a.spins + below + x);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    s[j] = static_cast<int>((w >> (8 * j)) & 0xFFu);
+                    d[j] = static_cast<int>((v >> (8 * j)) & 0xFFu);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (x + j < L) {
+                        s[j] = a.spins[here + x + j];
+                        d[j] = a.spins[below + x + j];
+                    }
+            }
+            if (x + 4 < L) s[4] = a.spins[here + x + 4];
+            const int first = a.spins[here];  // right neighbour of the row's last site
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                count_site(s[j], (x + j + 1 == L) ? first : s[j + 1], d[j], x + j < L, q, by_ballot, cn, cp, h);
+        }
+    }
+    if (by_ballot && (threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < kBallotQ; ++k)
+            if (k < q) {
+                atomicAdd(&h[k], cn[k]);
+                atomicAdd(&h[32 + k], cp[k]);
+            }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kRowWords; k += blockDim.x)
         if (h[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&row[k]), static_cast<unsigned long long>(h[k]));
 }
 
-
 // ---------------------------------------------------------------------------
 // Entry points.  k_*: one lattice per launch.  kb_*: one launch covers every
 // replica of a batch; workgroup b serves replica map[b], local block
 // b - begin[replica].
 // ---------------------------------------------------------------------------
+// Workgroups go to the eight XCDs of the chip in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  Renumbering the tiles so that every
+// XCD processes one contiguous run of them keeps neighbouring tiles, which
+// share cache lines of the spin and label arrays, in the same L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    return (n % kXcds) ? b : (b % kXcds) * (n / kXcds) + b / kXcds;
+}
+
 template <int kModel>
-__global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) { bond_local_tile<kModel>(a, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    bond_local_tile<kModel>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+}
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
 
 __global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
-    border_merge(a, static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+    border_merge(a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, blockIdx.x); }
 
 template <bool kVerify>
-__global__ void __launch_bounds__(256) k_flip(SweepArgs a) { flip<kVerify>(a, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    flip<kVerify>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+}
 
 __global__ void __launch_bounds__(256) k_counts(SweepArgs a) { counts(a, a.count_row, blockIdx.x, gridDim.x); }
 
@@ -735,7 +843,7 @@ __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
 __global__ void __launch_bounds__(256) kb_border_merge(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    border_merge(a, static_cast<size_t>(local) * blockDim.x + threadIdx.x);
+    border_merge(a, local * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) kb_flatten(BatchMap m) {
@@ -767,10 +875,11 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
     if (a.model == 1)
-        hipLaunchKernelGGL(k_bond_local<1>, dim3(a.tiles_x, a.tiles_y), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_bond_local<1>, grid, dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_bond_local<0>, dim3(a.tiles_x, a.tiles_y), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_bond_local<0>, grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -797,7 +906,7 @@ hipError_t launch_flatten(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(a.tiles_x), static_cast<unsigned>(a.tiles_y));
+    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
     if (verify)
         hipLaunchKernelGGL(k_flip<true>, grid, dim3(256), 0, s, a);
     else

@@ -383,17 +383,27 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
     if (flags & ~(SW_MEASURE | SW_VERIFY | SW_PROFILE)) return fail(SW_EINVAL, "unknown flag bits");
     const bool measure = flags & SW_MEASURE;
     const bool profile = flags & SW_PROFILE;
+    int64_t* const ring = reinterpret_cast<int64_t*>(c->base + c->lay.ring);
     int rows = 0;
+    auto next_row = [&](int64_t** row) -> int {
+        if (rows == 0) SW_HIP(c, hipMemsetAsync(ring, 0, static_cast<size_t>(kRing) * kRowWords * 8, c->stream));
+        *row = ring + static_cast<size_t>(rows) * kRowWords;
+        return SW_OK;
+    };
+    auto row_done = [&]() -> int {
+        if (++rows < kRing) return SW_OK;
+        const int st2 = flush_ring(c, rows);
+        rows = 0;
+        return st2;
+    };
     for (int32_t s = 0; s < nsweeps; ++s) {
         const bool verify = (flags & SW_VERIFY) && (s == nsweeps - 1);
-        if (measure && rows == 0) {
-            const int chunk = (nsweeps - s < kRing) ? (nsweeps - s) : kRing;
-            SW_HIP(c, hipMemsetAsync(c->base + c->lay.ring, 0, static_cast<size_t>(chunk) * kRowWords * 8, c->stream));
-        }
         st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(c->args, c->stream); });
         if (st) return st;
-        st = timed(c, profile, kKBlockMerge, [&] { return launch_block_merge(c->args, c->stream); });
-        if (st) return st;
+        if (c->args.merge_tiles > 1) {
+            st = timed(c, profile, kKBlockMerge, [&] { return launch_block_merge(c->args, c->stream); });
+            if (st) return st;
+        }
         st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(c->args, c->stream); });
         if (st) return st;
         st = timed(c, profile, kKFlatten, [&] { return launch_flatten(c->args, c->stream); });
@@ -403,14 +413,12 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         if (verify) c->have_canon = true;
         if (measure) {
             SweepArgs a = c->args;
-            a.count_row = reinterpret_cast<int64_t*>(c->base + c->lay.ring) + static_cast<size_t>(rows) * kRowWords;
+            st = next_row(&a.count_row);
+            if (st) return st;
             st = timed(c, profile, kKCounts, [&] { return launch_counts(a, c->stream); });
             if (st) return st;
-            if (++rows == kRing) {
-                st = flush_ring(c, rows);
-                if (st) return st;
-                rows = 0;
-            }
+            st = row_done();
+            if (st) return st;
         }
     }
     return flush_ring(c, rows);
@@ -528,8 +536,8 @@ int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* to
 int sw_set_schedule(sw_ctx* c, int32_t merge_tiles) {
     const int st = check_ctx(c);
     if (st) return st;
-    if (merge_tiles != 1 && merge_tiles != 2 && merge_tiles != 4 && merge_tiles != 8)
-        return fail(SW_EINVAL, "merge_tiles must be 1, 2, 4 or 8");
+    if (merge_tiles != 1 && merge_tiles != 2 && merge_tiles != 4)
+        return fail(SW_EINVAL, "merge_tiles must be 1, 2 or 4");
     c->args.merge_tiles = merge_tiles;
     return SW_OK;
 }
@@ -552,7 +560,7 @@ int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int best = c->args.merge_tiles;
     float best_ms = 0.0f;
-    for (int mt : {1, 2, 4, 8}) {
+    for (int mt : {1, 2, 4}) {
         if (e != hipSuccess || st) break;
         c->args.merge_tiles = mt;
         st = sw_sweep(c, 1, 0);

@@ -99,13 +99,23 @@ def test_many_sweeps_batch_call(swmc, orc):
     assert lat.measure()["t"] == 40
 
 
-@pytest.mark.parametrize("q,model,T", [(2, "potts", TC2), (3, "potts", TC3), (6, "clock", 0.9)])
-def test_measurements(swmc, orc, q, model, T):
-    L, therm, nmeas = 48, 20, 300
-    _say(f"[measure] q={q} {model}")
+# q <= 8: the counts of a sweep are taken by the next sweep's bond kernel (the
+# last sweep of a call by the count kernel); q = 10: the count kernel every
+# sweep.  1100 sweeps cross the 1024-row device ring; split calls hand the
+# pending count over to the count kernel at every call boundary.
+@pytest.mark.parametrize("q,model,T,L,calls", [
+    (2, "potts", TC2, 48, (300,)), (3, "potts", TC3, 48, (300,)), (6, "clock", 0.9, 48, (300,)),
+    (10, "potts", 1.0 / np.log(1.0 + np.sqrt(10.0)), 40, (300,)),
+    (2, "potts", TC2, 24, (1100,)), (3, "potts", TC3, 40, (1, 7, 1, 291)),
+    (3, "potts", TC3, 37, (120,)), (6, "clock", 0.9, 1030, (3,)),   # rows not a multiple of 4; > 1 step per row
+])
+def test_measurements(swmc, orc, q, model, T, L, calls):
+    therm, nmeas = 20, sum(calls)
+    _say(f"[measure] q={q} {model} L={L} calls={calls}")
     lat = swmc.Lattice(L, q, model, T=T, seed=31)
     lat.sweep(therm)
-    lat.sweep(nmeas, measure=True)
+    for n in calls:
+        lat.sweep(n, measure=True)
     ob = lat.measure()
     e, m2, s_final = orc.run(L, q, model, T, 1.0, 31, therm, nmeas)
     assert np.array_equal(lat.spins(), s_final)
@@ -150,3 +160,6 @@ def test_invalid_arguments_raise(swmc):
         lat.labels()  # no SW_VERIFY sweep yet
     with pytest.raises(swmc.SwError):
         lat.sweep(-1)
+    for mt in (0, 3, 8):
+        with pytest.raises(swmc.SwError):
+            lat.set_schedule(mt)
