@@ -24,7 +24,7 @@ namespace {
 constexpr int kSchedules[] = {1, 2, 4};  // first-level merge block sizes the tuner tries
 
 constexpr BatchKernel kListKernel[kNumLists] = {kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge,
-                                                kBKFlatten,   kBKFlip,      kBKCounts};
+                                                kBKFlatten,   kBKFlip,      kBKCounts,     kBKCountSum};
 
 struct Replica {
     sw_lattice p{};
@@ -384,18 +384,14 @@ int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags) {
     int rows = 0;
     for (int32_t s = 0; s < nsweeps; ++s) {
         const bool v = verify && (s == nsweeps - 1);
-        if (measure && rows == 0) {
-            const int chunk = (nsweeps - s < kRing) ? (nsweeps - s) : kRing;
-            for (auto& rp : b->reps)
-                SWB_HIP(b, hipMemsetAsync(b->base + rp.offset + rp.lay.ring, 0, static_cast<size_t>(chunk) * kRowWords * 8,
-                                          b->stream));
-        }
         st = enqueue_sweep(b, profile, v);
         if (st) return st;
         if (v)
             for (auto& rp : b->reps) rp.have_canon = true;
         if (measure) {
             st = launch_list(b, kLCounts, profile, static_cast<uint32_t>(rows));
+            if (st) return st;
+            st = launch_list(b, kLCountSum, profile, static_cast<uint32_t>(rows));
             if (st) return st;
             if (++rows == kRing) {
                 st = flush_rings(b, rows);
@@ -414,7 +410,6 @@ int sw_batch_measure(sw_batch* b, int32_t replica, sw_obs* out) {
     Replica& rp = b->reps[static_cast<size_t>(replica)];
     SweepArgs a = rp.args;
     a.count_row = reinterpret_cast<int64_t*>(b->base + rp.offset + rp.lay.scratch_row);
-    SWB_HIP(b, hipMemsetAsync(a.count_row, 0, kRowWords * 8, b->stream));
     SWB_HIP(b, launch_counts(a, b->stream));
     int64_t row[kRowWords];
     Control ctl;

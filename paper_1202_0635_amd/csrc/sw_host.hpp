@@ -25,7 +25,7 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v);
 
 struct Layout {
-    size_t ctl, spins, bond_r, bond_d, labels, canon, ring, scratch_row, table, total;
+    size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, ring, scratch_row, table, total;
 };
 Layout layout_of(const sw_lattice& p);
 
@@ -42,7 +42,7 @@ extern const Control kFreshControl;
 
 // Launch lists of the batched kernels: one launch per list and sweep covers
 // the workgroups of every lattice in a set.
-enum ListId { kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip, kLCounts, kNumLists };
+enum ListId { kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip, kLCounts, kLCountSum, kNumLists };
 // Workgroups list l needs for one lattice.
 uint32_t blocks_for(int l, const SweepArgs& a);
 

@@ -56,6 +56,7 @@ struct SweepArgs {
     const uint32_t* table;// cutoff table (Potts q*q; clock q^3)
     Control* ctl;
     int64_t* count_row;   // destination row of the count kernel (or null)
+    uint32_t* count_partial;  // [count_blocks(L)][kRowWords]: each count workgroup's bins
     int L, q, model, w64;
     int tiles_x, tiles_y;
     int merge_tiles;      // tiles per side of a first-level merge block (1: no block level)
@@ -83,7 +84,7 @@ __host__ __device__ inline uint32_t merge_blocks_x(int tiles_x, int mt) {
 // Batched launches: one launch covers the workgroups of every replica.
 enum BatchKernel {
     kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge, kBKFlatten, kBKFlip, kBKFlipVerify, kBKCounts,
-    kNumBatchKernels
+    kBKCountSum, kNumBatchKernels
 };
 struct BatchLaunch {
     const SweepArgs* reps;  // device replica table

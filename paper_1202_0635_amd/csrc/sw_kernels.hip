@@ -697,85 +697,175 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
 
 // ---------------------------------------------------------------------------
 // Integer counts of the current state: n[k] and the owned-bond histogram of
-// (s_j - s_i) mod q, accumulated into one int64 row.  Workgroup b takes rows
-// b, b + nblocks, ...; thread t takes four consecutive sites per step (one
-// 4-byte load of the row and one of the row below, the right neighbour of
-// the fourth site from the next thread), and the steps of a row are
-// unrolled so that their loads are in flight together.  For q <= kBallotQ
-// the counts are wave ballots summed in scalar registers; larger q uses LDS
-// atomics.  One global atomic per bin and workgroup.
+// (s_j - s_i) mod q.  Workgroup b takes rows b, b + nblocks, ...; thread t
+// takes groups of four consecutive sites, packed one byte per site in a
+// 32-bit word (the row, the row below, and the right neighbours), and four
+// groups of a row are loaded before any is counted.  q = 2 counts by
+// popcounts of the packed words; q <= 8 by wave ballots with the bins
+// unrolled (scalar registers); larger q by LDS atomics.  Each workgroup
+// stores its bins to its own partial row (thousands of global atomics on the
+// same few words would serialise) and one workgroup sums the partial rows.
 // ---------------------------------------------------------------------------
-constexpr int kBallotQ = 8;
+constexpr int kCountThreads = 256;
+constexpr int kGroupSpan = 4 * kCountThreads;  // sites of a row per step of the workgroup
+constexpr int kGroups = 4;                     // steps of a row whose loads are issued together
 
-__device__ __forceinline__ void count_site(int s, int sr, int sd, bool ok, int q, bool by_ballot, uint32_t* cn,
-                                           uint32_t* cp, uint32_t* h) {
-    int dr = sr - s, dd = sd - s;
-    if (dr < 0) dr += q;
-    if (dd < 0) dd += q;
-    if (by_ballot) {
-#pragma unroll
-        for (int k = 0; k < kBallotQ; ++k)
-            if (k < q) {
-                cn[k] += static_cast<uint32_t>(__popcll(__ballot(ok && s == k)));
-                cp[k] += static_cast<uint32_t>(__popcll(__ballot(ok && dr == k)) + __popcll(__ballot(ok && dd == k)));
-            }
-    } else if (ok) {
-        atomicAdd(&h[s], 1u);
-        atomicAdd(&h[32 + dr], 1u);
-        atomicAdd(&h[32 + dd], 1u);
+struct Group4 {
+    uint32_t w, wr, v;  // spins of four sites, of their right and lower neighbours
+    int n;              // sites of the group inside the row (0..4)
+};
+
+__device__ __forceinline__ Group4 load_group(const int8_t* spins, uint32_t here, uint32_t below, int x, int L,
+                                             bool aligned, int first) {
+    Group4 g{0u, 0u, 0u, max(0, min(4, L - x))};
+    if (aligned && g.n == 4) {
+        g.w = *reinterpret_cast<const uint32_t*>(spins + here + x);
+        g.v = *reinterpret_cast<const uint32_t*>(spins + below + x);
+        const uint32_t next = (x + 4 < L) ? static_cast<uint8_t>(spins[here + x + 4]) : static_cast<uint32_t>(first);
+        g.wr = (g.w >> 8) | (next << 24);
+    } else {
+        for (int j = 0; j < g.n; ++j) {
+            g.w |= static_cast<uint32_t>(static_cast<uint8_t>(spins[here + x + j])) << (8 * j);
+            g.v |= static_cast<uint32_t>(static_cast<uint8_t>(spins[below + x + j])) << (8 * j);
+            const uint32_t r = (x + j + 1 < L) ? static_cast<uint8_t>(spins[here + x + j + 1]) : static_cast<uint32_t>(first);
+            g.wr |= r << (8 * j);
+        }
     }
+    return g;
 }
 
-__device__ __forceinline__ void counts(const SweepArgs& a, int64_t* row, const uint32_t block, const uint32_t nblocks) {
-    __shared__ uint32_t h[kRowWords];
-    for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) h[k] = 0;
-    __syncthreads();
-    const int L = a.L, q = a.q;
-    const bool by_ballot = q <= kBallotQ;
+// Calls f(group) for every group of four sites of this workgroup's rows.
+template <typename F>
+__device__ __forceinline__ void for_groups(const SweepArgs& a, uint32_t block, uint32_t nblocks, F&& f) {
+    const int L = a.L;
     const bool aligned = (L & 3) == 0;
-    uint32_t cn[kBallotQ] = {}, cp[kBallotQ] = {};
-    const int span = 4 * static_cast<int>(blockDim.x);
     for (int y = static_cast<int>(block); y < L; y += static_cast<int>(nblocks)) {
         const uint32_t here = __umul24(y, L);
         const uint32_t below = __umul24((y + 1 == L) ? 0 : y + 1, L);
-#pragma unroll 4
-        for (int x0 = 0; x0 < L; x0 += span) {
-            const int x = x0 + 4 * static_cast<int>(threadIdx.x);
-            int s[5] = {0, 0, 0, 0, 0}, d[4] = {0, 0, 0, 0};
-            if (aligned && x + 4 <= L) {
-                const uint32_t w = *reinterpret_cast<const uint32_t*>(a.spins + here + x);
-                const uint32_t v = *reinterpret_cast<const uint32_t*>(a.spins + below + x);
+        const int first = static_cast<uint8_t>(a.spins[here]);  // right neighbour of the row's last site
+        for (int xb = 0; xb < L; xb += kGroups * kGroupSpan) {
+            Group4 g[kGroups];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    s[j] = static_cast<int>((w >> (8 * j)) & 0xFFu);
-                    d[j] = static_cast<int>((v >> (8 * j)) & 0xFFu);
-                }
-            } else {
+            for (int u = 0; u < kGroups; ++u)
+                g[u] = load_group(a.spins, here, below, xb + u * kGroupSpan + 4 * static_cast<int>(threadIdx.x), L,
+                                  aligned, first);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (x + j < L) {
-                        s[j] = a.spins[here + x + j];
-                        d[j] = a.spins[below + x + j];
-                    }
-            }
-            if (x + 4 < L) s[4] = a.spins[here + x + 4];
-            const int first = a.spins[here];  // right neighbour of the row's last site
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                count_site(s[j], (x + j + 1 == L) ? first : s[j + 1], d[j], x + j < L, q, by_ballot, cn, cp, h);
+            for (int u = 0; u < kGroups; ++u) f(g[u]);
         }
     }
-    if (by_ballot && (threadIdx.x & 63) == 0) {
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
-        for (int k = 0; k < kBallotQ; ++k)
-            if (k < q) {
-                atomicAdd(&h[k], cn[k]);
-                atomicAdd(&h[32 + k], cp[k]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// q = 2: bytes are 0 or 1, so a popcount of a packed word (or of the xor of
+// two) counts ones (or unequal pairs) among its valid bytes.
+__device__ __forceinline__ void count_q2(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h) {
+    uint32_t sites = 0, ones = 0, diff = 0;
+    for_groups(a, block, nblocks, [&](const Group4& g) {
+        const uint32_t m = (g.n >= 4) ? 0xFFFFFFFFu : ((1u << (8 * g.n)) - 1u);
+        sites += static_cast<uint32_t>(g.n);
+        ones += __popc(g.w & m);
+        diff += __popc((g.w ^ g.wr) & m) + __popc((g.w ^ g.v) & m);
+    });
+    sites = wave_sum(sites);
+    ones = wave_sum(ones);
+    diff = wave_sum(diff);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&h[0], sites - ones);
+        atomicAdd(&h[1], ones);
+        atomicAdd(&h[32], 2u * sites - diff);
+        atomicAdd(&h[33], diff);
+    }
+}
+
+template <int Q>
+__device__ __forceinline__ void count_ballot(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h) {
+    uint32_t cn[Q] = {}, cp[Q] = {};
+    for_groups(a, block, nblocks, [&](const Group4& g) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool ok = j < g.n;
+            const int s = static_cast<int>((g.w >> (8 * j)) & 0xFFu);
+            int dr = static_cast<int>((g.wr >> (8 * j)) & 0xFFu) - s;
+            int dd = static_cast<int>((g.v >> (8 * j)) & 0xFFu) - s;
+            if (dr < 0) dr += Q;
+            if (dd < 0) dd += Q;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                cn[k] += static_cast<uint32_t>(__popcll(__ballot(ok && s == k)));
+                cp[k] += static_cast<uint32_t>(__popcll(__ballot(ok && dr == k)) + __popcll(__ballot(ok && dd == k)));
             }
+        }
+    });
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            atomicAdd(&h[k], cn[k]);
+            atomicAdd(&h[32 + k], cp[k]);
+        }
+    }
+}
+
+__device__ __forceinline__ void count_lds(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h) {
+    const int q = a.q;
+    for_groups(a, block, nblocks, [&](const Group4& g) {
+        for (int j = 0; j < g.n; ++j) {
+            const int s = static_cast<int>((g.w >> (8 * j)) & 0xFFu);
+            int dr = static_cast<int>((g.wr >> (8 * j)) & 0xFFu) - s;
+            int dd = static_cast<int>((g.v >> (8 * j)) & 0xFFu) - s;
+            if (dr < 0) dr += q;
+            if (dd < 0) dd += q;
+            atomicAdd(&h[s], 1u);
+            atomicAdd(&h[32 + dr], 1u);
+            atomicAdd(&h[32 + dd], 1u);
+        }
+    });
+}
+
+__device__ __forceinline__ void counts(const SweepArgs& a, const uint32_t block, const uint32_t nblocks) {
+    __shared__ uint32_t h[kRowWords];
+    for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    switch (a.q) {
+        case 2: count_q2(a, block, nblocks, h); break;
+        case 3: count_ballot<3>(a, block, nblocks, h); break;
+        case 4: count_ballot<4>(a, block, nblocks, h); break;
+        case 5: count_ballot<5>(a, block, nblocks, h); break;
+        case 6: count_ballot<6>(a, block, nblocks, h); break;
+        case 7: count_ballot<7>(a, block, nblocks, h); break;
+        case 8: count_ballot<8>(a, block, nblocks, h); break;
+        default: count_lds(a, block, nblocks, h); break;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kRowWords; k += blockDim.x)
-        if (h[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&row[k]), static_cast<unsigned long long>(h[k]));
+    uint32_t* part = a.count_partial + static_cast<size_t>(block) * kRowWords;
+    for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) part[k] = h[k];
+}
+
+// Sum of the partial rows of the count workgroups into row[0..kRowWords):
+// thread t adds partial rows t, t + blockDim, ... for every bin in use, a
+// wave sum follows, and one LDS add per wave and bin.
+constexpr int kCountSumThreads = 1024;
+
+__device__ __forceinline__ void count_sum(const SweepArgs& a, int64_t* row) {
+    __shared__ unsigned long long tot[kRowWords];
+    for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) tot[k] = 0;
+    __syncthreads();
+    const uint32_t nb = count_blocks(a.L);
+    const int q = a.q;
+    for (int k = 0; k < 2 * q; ++k) {
+        const int bin = (k < q) ? k : 32 + (k - q);
+        unsigned long long v = 0;
+        for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) v += a.count_partial[static_cast<size_t>(b) * kRowWords + bin];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&tot[bin], v);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) row[k] = static_cast<int64_t>(tot[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +902,9 @@ __global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
     flip<kVerify>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-__global__ void __launch_bounds__(256) k_counts(SweepArgs a) { counts(a, a.count_row, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(kCountThreads) k_counts(SweepArgs a) { counts(a, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(kCountSumThreads) k_count_sum(SweepArgs a) { count_sum(a, a.count_row); }
 
 struct BatchMap {
     const SweepArgs* reps;  // replica table
@@ -859,11 +951,16 @@ __global__ void __launch_bounds__(256) kb_flip(BatchMap m) {
     flip<kVerify>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
 }
 
-__global__ void __launch_bounds__(256) kb_counts(BatchMap m, uint32_t row) {
+__global__ void __launch_bounds__(kCountThreads) kb_counts(BatchMap m) {
     uint32_t local;
-    const uint32_t r = batch_replica(m, &local);
-    const SweepArgs& a = m.reps[r];
-    counts(a, a.count_row + static_cast<size_t>(row) * kRowWords, local, count_blocks(a.L));
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    counts(a, local, count_blocks(a.L));
+}
+
+__global__ void __launch_bounds__(kCountSumThreads) kb_count_sum(BatchMap m, uint32_t row) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    count_sum(a, a.count_row + static_cast<size_t>(row) * kRowWords);
 }
 
 }  // namespace
@@ -915,7 +1012,8 @@ hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
 }
 
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_counts, dim3(count_blocks(a.L)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_counts, dim3(count_blocks(a.L)), dim3(kCountThreads), 0, s, a);
+    hipLaunchKernelGGL(k_count_sum, dim3(1), dim3(kCountSumThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -935,7 +1033,8 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
         case kBKFlatten: hipLaunchKernelGGL(kb_flatten, grid, dim3(256), 0, s, m); break;
         case kBKFlip: hipLaunchKernelGGL(kb_flip<false>, grid, dim3(256), 0, s, m); break;
         case kBKFlipVerify: hipLaunchKernelGGL(kb_flip<true>, grid, dim3(256), 0, s, m); break;
-        case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(256), 0, s, m, row); break;
+        case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(kCountThreads), 0, s, m); break;
+        case kBKCountSum: hipLaunchKernelGGL(kb_count_sum, grid, dim3(kCountSumThreads), 0, s, m, row); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -117,6 +117,7 @@ Layout layout_of(const sw_lattice& p) {
     l.bond_d = o; o += up(L * w64 * 8);
     l.labels = o; o += up(N * 4);
     l.canon = o; o += up(N * 4);
+    l.count_partial = o; o += up(static_cast<size_t>(count_blocks(p.L)) * kRowWords * 4);
     l.ring = o; o += up(static_cast<size_t>(kRing) * kRowWords * 8);
     l.scratch_row = o; o += up(kRowWords * 8);
     l.table = o; o += up(table_entries(p) * 4);
@@ -164,6 +165,7 @@ uint32_t blocks_for(int l, const SweepArgs& a) {
         case kLFlatten: return div_up((static_cast<uint64_t>(a.tiles_x) + a.tiles_y) * L, 256);
         case kLFlip: return static_cast<uint32_t>(a.tiles_x * a.tiles_y);
         case kLCounts: return count_blocks(a.L);
+        case kLCountSum: return 1u;
         default: return 0u;
     }
 }
@@ -175,6 +177,7 @@ SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     a.bond_d = reinterpret_cast<uint64_t*>(base + lay.bond_d);
     a.labels = reinterpret_cast<uint32_t*>(base + lay.labels);
     a.canon = reinterpret_cast<uint32_t*>(base + lay.canon);
+    a.count_partial = reinterpret_cast<uint32_t*>(base + lay.count_partial);
     a.table = reinterpret_cast<const uint32_t*>(base + lay.table);
     a.ctl = reinterpret_cast<Control*>(base + lay.ctl);
     a.count_row = nullptr;
@@ -386,7 +389,6 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
     int64_t* const ring = reinterpret_cast<int64_t*>(c->base + c->lay.ring);
     int rows = 0;
     auto next_row = [&](int64_t** row) -> int {
-        if (rows == 0) SW_HIP(c, hipMemsetAsync(ring, 0, static_cast<size_t>(kRing) * kRowWords * 8, c->stream));
         *row = ring + static_cast<size_t>(rows) * kRowWords;
         return SW_OK;
     };
@@ -430,7 +432,6 @@ int sw_measure(sw_ctx* c, sw_obs* out) {
     if (!out) return fail(SW_EINVAL, "null sw_obs");
     SweepArgs a = c->args;
     a.count_row = reinterpret_cast<int64_t*>(c->base + c->lay.scratch_row);
-    SW_HIP(c, hipMemsetAsync(a.count_row, 0, kRowWords * 8, c->stream));
     SW_HIP(c, launch_counts(a, c->stream));
     int64_t row[kRowWords];
     Control ctl;

@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kSweepLists[] = {kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip};
 constexpr BatchKernel kKernelOf[kNumLists] = {kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge,
-                                              kBKFlatten,   kBKFlip,      kBKCounts};
+                                              kBKFlatten,   kBKFlip,      kBKCounts,     kBKCountSum};
 
 // First-fit allocator over [0, size) with coalescing of freed neighbours.
 class PoolAllocator {
@@ -194,7 +194,7 @@ int rebuild(sw_server* s) {
     for (int l = 0; l < kNumLists; ++l) {
         s->h_map[l].clear();
         s->h_begin[l].assign(n, 0u);
-        if (l == kLCounts) {  // measurements of retiring lattices use the single-lattice launch
+        if (l == kLCounts || l == kLCountSum) {  // retiring lattices are counted by the single-lattice launch
             s->blocks[l] = 0;
             total += n;
             continue;
@@ -231,7 +231,6 @@ int retire(sw_server* s, Slot& sl) {
     char* base = s->pool + sl.off;
     SweepArgs a = sl.args;
     a.count_row = reinterpret_cast<int64_t*>(base + sl.lay.scratch_row);
-    SWS_HIP(s, hipMemsetAsync(a.count_row, 0, kRowWords * 8, s->stream));
     SWS_HIP(s, launch_counts(a, s->stream));
     int64_t row[kRowWords];
     Control ctl;

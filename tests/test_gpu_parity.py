@@ -108,6 +108,7 @@ def test_many_sweeps_batch_call(swmc, orc):
     (10, "potts", 1.0 / np.log(1.0 + np.sqrt(10.0)), 40, (300,)),
     (2, "potts", TC2, 24, (1100,)), (3, "potts", TC3, 40, (1, 7, 1, 291)),
     (3, "potts", TC3, 37, (120,)), (6, "clock", 0.9, 1030, (3,)),   # rows not a multiple of 4; > 1 step per row
+    (2, "potts", TC2, 45, (60,)), (2, "clock", 1.2, 1030, (2,)), (8, "potts", 0.7, 50, (40,)),
 ])
 def test_measurements(swmc, orc, q, model, T, L, calls):
     therm, nmeas = 20, sum(calls)
