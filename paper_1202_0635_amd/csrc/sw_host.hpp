@@ -25,7 +25,8 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v);
 
 struct Layout {
-    size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, ring, scratch_row, table, total;
+    size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, border_roots, border_bonds, ring, scratch_row, table,
+        total;
 };
 Layout layout_of(const sw_lattice& p);
 

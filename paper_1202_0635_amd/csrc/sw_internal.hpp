@@ -35,6 +35,19 @@ constexpr uint32_t kInit = 4;
 constexpr uint32_t kRootFlag = 0x80000000u;
 
 constexpr int kRing = 1024;      // per-sweep count rows kept on the device
+
+// Per-tile border record written by the bond kernel.  Edge e of border_roots:
+// 0 right column, 1 bottom row, 2 left column, 3 top row (the last valid
+// column / row of a ragged tile).  Masks: bit = row (columns) or column (rows).
+enum BorderMask {
+    kRightR = 0,   // right bonds of the right column (they leave the tile)
+    kRightD = 1,   // down bonds of the right column
+    kLeftD = 2,    // down bonds of the left column
+    kBottomD = 3,  // down bonds of the bottom row (they leave the tile)
+    kBottomR = 4,  // right bonds of the bottom row
+    kTopR = 5,     // right bonds of the top row
+    kBorderMasks = 8
+};
 constexpr int kRowWords = 64;    // int64 per count row: hist[32], pair_hist[32]
 
 // Device control block at the start of the arena.
@@ -57,6 +70,8 @@ struct SweepArgs {
     Control* ctl;
     int64_t* count_row;   // destination row of the count kernel (or null)
     uint32_t* count_partial;  // [count_blocks(L)][kRowWords]: each count workgroup's bins
+    uint32_t* border_roots;   // [tiles][4][64]: tile-local root (site index) of each edge site
+    uint64_t* border_bonds;   // [tiles][kBorderMasks]: the bond bits the border joins read
     int L, q, model, w64;
     int tiles_x, tiles_y;
     int merge_tiles;      // tiles per side of a first-level merge block (1: no block level)

@@ -116,14 +116,11 @@ __device__ __forceinline__ uint32_t c_find(uint32_t* lab, uint32_t x, uint32_t* 
     return x;
 }
 
-// Join the clusters of sites a and b: the larger root is linked under the
-// smaller one by compare-and-swap on its root word.  The first attempt walks
-// the forest through the caches; after a failed swap the walk uses coherent
-// loads (and halves the paths it visits).
-__device__ void g_union(uint32_t* lab, uint32_t a, uint32_t b) {
-    uint32_t wa, wb;
-    a = c_find(lab, a, &wa);
-    b = c_find(lab, b, &wb);
+// Join the clusters whose roots were found (through the caches) as a and b,
+// with root words wa and wb: the larger root is linked under the smaller one
+// by compare-and-swap on its root word; after a failed swap the walk uses
+// coherent loads (and halves the paths it visits).
+__device__ void g_union_roots(uint32_t* lab, uint32_t a, uint32_t wa, uint32_t b, uint32_t wb) {
     while (a != b) {
         if (a > b) {
             uint32_t tmp = a;
@@ -146,45 +143,50 @@ __device__ __forceinline__ int mirror_of(uint64_t t, int q, uint32_t k0, uint32_
     return static_cast<int>(qmap(draw(0u, t, kMirror, k0, k1).w0, static_cast<uint32_t>(q)));
 }
 
-__device__ __forceinline__ uint32_t bond_bit(const uint64_t* bonds, int w64, int x, int y) {
-    return static_cast<uint32_t>(bonds[__umul24(y, w64) + (static_cast<uint32_t>(x) >> 6)] >> (x & 63)) & 1u;
-}
 
 // ---------------------------------------------------------------------------
-// Bonds that leave a tile (or wrap around the torus).  A bond is skipped
-// when the neighbouring bond along the same border joins the same two
-// tile-local sets (both its ends are tile-internal neighbours).
+// Bonds that leave a tile (or wrap around the torus), read from the tiles'
+// border records.  A bond is skipped when the bond before it on the same
+// border joins the same two tile-local sets (both its ends are tile-internal
+// neighbours of the skipped bond's ends).  The ends are returned as their
+// tile-local roots.
 // ---------------------------------------------------------------------------
 struct BorderBond {
     bool active;
     uint32_t i, j;
 };
 
+__device__ __forceinline__ uint32_t bit(uint64_t m, int k) { return static_cast<uint32_t>(m >> k) & 1u; }
+
 // Right-edge bond of tile column tx in row y (wrapping to column 0 after the
-// last column).  Skipped when row y-1 of the same tile row already joins the
-// same two tile-local sets: both of its ends are tile-internal neighbours.
+// last column).
 __device__ __forceinline__ BorderBond vertical_border_bond(const SweepArgs& a, int tx, int y) {
-    const int L = a.L;
-    const int xe = min((tx + 1) * kTileW, L) - 1;
-    const int xr = (xe + 1 == L) ? 0 : xe + 1;
-    if (!bond_bit(a.bond_r, a.w64, xe, y)) return {false, 0u, 0u};
-    if ((y % kTileH) != 0 && bond_bit(a.bond_r, a.w64, xe, y - 1) && bond_bit(a.bond_d, a.w64, xe, y - 1) &&
-        bond_bit(a.bond_d, a.w64, xr, y - 1))
+    const int ty = y / kTileH, ly = y - ty * kTileH;
+    const int t = ty * a.tiles_x + tx;
+    const int tr = ty * a.tiles_x + ((tx + 1 == a.tiles_x) ? 0 : tx + 1);
+    const uint64_t* m = a.border_bonds + static_cast<size_t>(t) * kBorderMasks;
+    const uint64_t rr = m[kRightR];
+    if (!bit(rr, ly)) return {false, 0u, 0u};
+    if (ly != 0 && bit(rr, ly - 1) && bit(m[kRightD], ly - 1) &&
+        bit(a.border_bonds[static_cast<size_t>(tr) * kBorderMasks + kLeftD], ly - 1))
         return {false, 0u, 0u};
-    const uint32_t row = __umul24(y, L);
-    return {true, row + static_cast<uint32_t>(xe), row + static_cast<uint32_t>(xr)};
+    return {true, a.border_roots[(static_cast<size_t>(t) * 4 + 0) * kTileW + ly],
+            a.border_roots[(static_cast<size_t>(tr) * 4 + 2) * kTileW + ly]};
 }
 
 // Bottom-edge bond of tile row ty in column x (wrapping to row 0).
 __device__ __forceinline__ BorderBond horizontal_border_bond(const SweepArgs& a, int ty, int x) {
-    const int L = a.L;
-    const int ye = min((ty + 1) * kTileH, L) - 1;
-    const int yd = (ye + 1 == L) ? 0 : ye + 1;
-    if (!bond_bit(a.bond_d, a.w64, x, ye)) return {false, 0u, 0u};
-    if ((x % kTileW) != 0 && bond_bit(a.bond_d, a.w64, x - 1, ye) && bond_bit(a.bond_r, a.w64, x - 1, ye) &&
-        bond_bit(a.bond_r, a.w64, x - 1, yd))
+    const int tx = x / kTileW, lx = x - tx * kTileW;
+    const int t = ty * a.tiles_x + tx;
+    const int td = ((ty + 1 == a.tiles_y) ? 0 : ty + 1) * a.tiles_x + tx;
+    const uint64_t* m = a.border_bonds + static_cast<size_t>(t) * kBorderMasks;
+    const uint64_t bd = m[kBottomD];
+    if (!bit(bd, lx)) return {false, 0u, 0u};
+    if (lx != 0 && bit(bd, lx - 1) && bit(m[kBottomR], lx - 1) &&
+        bit(a.border_bonds[static_cast<size_t>(td) * kBorderMasks + kTopR], lx - 1))
         return {false, 0u, 0u};
-    return {true, __umul24(ye, L) + static_cast<uint32_t>(x), __umul24(yd, L) + static_cast<uint32_t>(x)};
+    return {true, a.border_roots[(static_cast<size_t>(t) * 4 + 1) * kTileW + lx],
+            a.border_roots[(static_cast<size_t>(td) * 4 + 3) * kTileW + lx]};
 }
 
 // ---------------------------------------------------------------------------
@@ -228,8 +230,10 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // Site indices stay below 2^31 (L <= 46340), so 32-bit arithmetic with
     // 24-bit multiplies (L < 2^16) replaces 64-bit address products.
     const uint32_t tile_base = __umul24(y0, L) + static_cast<uint32_t>(x0);
+    const size_t tile = static_cast<size_t>(ty) * a.tiles_x + tx;
     const bool col_ok = x < L;
     const int nvalid = min(kTileW, L - x0);
+    const int nrows = min(kTileH, L - y0);
     // lanes whose right bond stays inside the tile (not the last column, no wrap)
     const uint64_t in_tile_r = (nvalid >= 64) ? (~0ull >> 1) : ((1ull << (nvalid - 1)) - 1ull);
     const uint64_t t = a.ctl->t;
@@ -347,6 +351,22 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 a.bond_d[wi] = raw_d[ly];
         }
     }
+    // Border record, bond masks (lane = row of the tile for the column masks).
+    if (wave == kWaves - 1) {
+        const bool rowok = lane < nrows;
+        const uint64_t rr = raw_r[lane], dd = raw_d[lane];
+        const uint64_t right_r = __ballot(rowok && ((rr >> (nvalid - 1)) & 1ull));
+        const uint64_t right_d = __ballot(rowok && ((dd >> (nvalid - 1)) & 1ull));
+        const uint64_t left_d = __ballot(rowok && (dd & 1ull));
+        uint64_t v = 0;
+        if (lane == kRightR) v = right_r;
+        if (lane == kRightD) v = right_d;
+        if (lane == kLeftD) v = left_d;
+        if (lane == kBottomD) v = raw_d[nrows - 1];
+        if (lane == kBottomR) v = raw_r[nrows - 1];
+        if (lane == kTopR) v = raw_r[0];
+        if (lane < kBorderMasks) a.border_bonds[tile * kBorderMasks + lane] = v;
+    }
     // Phase 2: each wave labels its strip of rows in raster order, as the
     // Hoshen-Kopelman scan does (Sec. 2): a run of the current row takes the
     // smallest root among the sites above it that it is bonded to (or becomes
@@ -410,6 +430,24 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
         rootreg[r] = P[P[self]];
     }
+    // Border record, edge roots: edge = wave (right column, bottom row, left
+    // column, top row), position = lane.
+    static_assert(kWaves == 4 && kTileW == 64 && kTileH == 64, "one wave per tile edge, one lane per position");
+    {
+        int ly = lane, lx = lane;
+        bool valid = lane < nrows;
+        if (wave == 0) lx = nvalid - 1;
+        if (wave == 2) lx = 0;
+        if (wave == 1 || wave == 3) {
+            ly = (wave == 1) ? nrows - 1 : 0;
+            valid = lane < nvalid;
+        }
+        if (valid) {
+            const uint32_t root = P[P[ly * kTileW + lx]];
+            a.border_roots[(tile * 4 + static_cast<size_t>(wave)) * kTileW + lane] =
+                tile_base + __umul24(root >> 6, L) + (root & 63u);
+        }
+    }
     __syncthreads();
     uint32_t* list = P + ly_base * kTileW;  // this wave's slice of P holds its root list
     uint32_t nroots = 0;
@@ -463,11 +501,10 @@ __device__ __forceinline__ BorderBond border_bond(const SweepArgs& a, uint32_t g
 
 // ---------------------------------------------------------------------------
 // Merge, level 1: one workgroup per block of mt x mt tiles (mt <= 4) joins
-// the block's inner tile borders in LDS.  The ends of every active inner
-// border bond are mapped to their tile-local roots (one load each: a site's
-// label word names its tile-local root), the roots are entered in an LDS
-// hash table (slot = node), and the unions run on an LDS forest whose links
-// always go from the larger site index to the smaller.  Finally every node
+// the block's inner tile borders in LDS.  The tile-local roots at the ends of
+// every active inner border bond (from the border records) are entered in an
+// LDS hash table (slot = node), and the unions run on an LDS forest whose
+// links always go from the larger site index to the smaller.  Finally every node
 // that is no longer a root has its global root word replaced by a link to
 // its block root.  The nodes belong to this block only, so nothing here
 // races with another workgroup.
@@ -518,11 +555,6 @@ __device__ __forceinline__ void node_union(uint32_t* par, const uint32_t* keys, 
     }
 }
 
-__device__ __forceinline__ uint32_t tile_root(const uint32_t* lab, uint32_t i) {
-    const uint32_t w = lab[i];
-    return (w & kRootFlag) ? i : w;
-}
-
 __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, const int by) {
     __shared__ uint32_t keys[kHashSlots];
     __shared__ uint32_t par[kHashSlots];
@@ -556,8 +588,8 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
         else
             b = horizontal_border_bond(a, tya + (k - nv) / ncols, xa + (k - nv) % ncols);
         if (!b.active) continue;
-        ends[r][0] = hash_insert(keys, tile_root(a.labels, b.i));
-        ends[r][1] = hash_insert(keys, tile_root(a.labels, b.j));
+        ends[r][0] = hash_insert(keys, b.i);
+        ends[r][1] = hash_insert(keys, b.j);
     }
     __syncthreads();
 #pragma unroll
@@ -577,24 +609,40 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
 // device-wide lock-free union.  Thread g < nbx*L: right edge of the last tile
 // column of block column g / L; the rest: bottom edges of block rows.
 // ---------------------------------------------------------------------------
+// Neighbouring lanes take neighbouring sites of one border and mostly find
+// the same two roots; a lane whose pair of roots equals the previous lane's
+// leaves the union to that lane.  (Every link ever stored points to an
+// ancestor, so equal found roots mean equal sets; the first lane of a run of
+// equal pairs does the union.)
 __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t gid) {
     if (!a.ctl->live) return;
     const BorderBond b = border_bond(a, gid, a.merge_tiles);
-    if (b.active) g_union(a.labels, b.i, b.j);
+    uint32_t ra = kRootFlag, rb = kRootFlag, wa = 0, wb = 0;
+    if (b.active) {
+        ra = c_find(a.labels, b.i, &wa);
+        rb = c_find(a.labels, b.j, &wb);
+        if (ra > rb) {
+            uint32_t tmp = ra;
+            ra = rb;
+            rb = tmp;
+            tmp = wa;
+            wa = wb;
+            wb = tmp;
+        }
+    }
+    const uint32_t pa = __shfl_up(ra, 1, 64), pb = __shfl_up(rb, 1, 64);
+    const bool repeat = (threadIdx.x & 63) != 0 && pa == ra && pb == rb;
+    if (b.active && ra != rb && !repeat) g_union_roots(a.labels, ra, wa, rb, wb);
 }
 
-// After the merge: every linked tile-local root at the end of a border bond
-// is pointed straight at its cluster root, so that any site reaches the root
-// word in at most three loads (site -> tile-local root -> root).
-__device__ __forceinline__ void flatten_from(uint32_t* lab, uint32_t e) {
-    uint32_t w = lab[e];
-    uint32_t r = e;
-    if (!(w & kRootFlag)) {
-        r = w;
-        w = lab[r];
-    }
-    if (w & kRootFlag) return;  // the tile-local root is still a cluster root
-    uint32_t x = w;             // walk to the root, halving the path on the way
+// After the merge: every tile-local root at the end of a border bond that
+// has been linked is pointed straight at its cluster root, so that any site
+// reaches the root word in at most two loads (site -> tile-local root ->
+// root).  The walk halves the path on the way.
+__device__ __forceinline__ void flatten_root(uint32_t* lab, uint32_t r) {
+    const uint32_t w = lab[r];
+    if (w & kRootFlag) return;  // still a cluster root
+    uint32_t x = w;
     uint32_t wx = lab[x];
     while (!(wx & kRootFlag)) {
         const uint32_t w2 = lab[wx];
@@ -615,9 +663,12 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
     // flip only needs the mirror recorded by k_bond_local.
     if (block == 0 && threadIdx.x == 0) a.ctl->t += 1;
     const BorderBond b = border_bond(a, block * blockDim.x + threadIdx.x, 1);
-    if (!b.active) return;
-    flatten_from(a.labels, b.i);
-    flatten_from(a.labels, b.j);
+    // a tile-local root that the previous lane also reaches is left to it
+    const uint32_t i = b.active ? b.i : kRootFlag, j = b.active ? b.j : kRootFlag;
+    const uint32_t pi = __shfl_up(i, 1, 64), pj = __shfl_up(j, 1, 64);
+    const bool first = (threadIdx.x & 63) == 0;
+    if (b.active && (first || pi != i)) flatten_root(a.labels, i);
+    if (b.active && (first || pj != j)) flatten_root(a.labels, j);
 }
 
 // ---------------------------------------------------------------------------

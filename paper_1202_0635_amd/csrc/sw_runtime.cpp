@@ -118,6 +118,9 @@ Layout layout_of(const sw_lattice& p) {
     l.labels = o; o += up(N * 4);
     l.canon = o; o += up(N * 4);
     l.count_partial = o; o += up(static_cast<size_t>(count_blocks(p.L)) * kRowWords * 4);
+    const size_t tiles = ((L + kTileW - 1) / kTileW) * ((L + kTileH - 1) / kTileH);
+    l.border_roots = o; o += up(tiles * 4 * kTileW * 4);
+    l.border_bonds = o; o += up(tiles * kBorderMasks * 8);
     l.ring = o; o += up(static_cast<size_t>(kRing) * kRowWords * 8);
     l.scratch_row = o; o += up(kRowWords * 8);
     l.table = o; o += up(table_entries(p) * 4);
@@ -178,6 +181,8 @@ SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     a.labels = reinterpret_cast<uint32_t*>(base + lay.labels);
     a.canon = reinterpret_cast<uint32_t*>(base + lay.canon);
     a.count_partial = reinterpret_cast<uint32_t*>(base + lay.count_partial);
+    a.border_roots = reinterpret_cast<uint32_t*>(base + lay.border_roots);
+    a.border_bonds = reinterpret_cast<uint64_t*>(base + lay.border_bonds);
     a.table = reinterpret_cast<const uint32_t*>(base + lay.table);
     a.ctl = reinterpret_cast<Control*>(base + lay.ctl);
     a.count_row = nullptr;
