@@ -218,7 +218,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     __shared__ uint64_t raw_r[kTileH];       // right-bond masks of the tile's rows
     __shared__ uint64_t raw_d[kTileH];       // down-bond masks
     __shared__ uint32_t cut[kClock ? 32 * 32 : 1];
-    __shared__ int halo[kTileH];             // spins of the column right of the tile
+    __shared__ uint8_t halo[kTileH];         // spins of the column right of the tile
     __shared__ uint32_t slot[kWaves][kTileW];  // per-run minimum of the labelling pass
     __shared__ uint32_t ntie;
 
@@ -257,7 +257,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     if (threadIdx.x < kTileH) {
         const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
         const int yh = y0 + static_cast<int>(threadIdx.x);
-        halo[threadIdx.x] = (yh < L) ? a.spins[__umul24(yh, L) + static_cast<uint32_t>(xh)] : 0;
+        halo[threadIdx.x] = (yh < L) ? static_cast<uint8_t>(a.spins[__umul24(yh, L) + static_cast<uint32_t>(xh)]) : 0;
     }
     __syncthreads();
 
@@ -271,7 +271,12 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
     const bool edge_lane = (lane == nvalid - 1);
 
-    // Phase 1: decisions on the high bytes; ties go to the list.
+    // Phase 1: decisions on the high bytes; ties go to the list.  The right
+    // neighbour comes from the next lane by a DPP wave shift; the edge lane
+    // takes it from the halo, whose RPW bytes for this wave are read once.
+    const uint4 hv = *reinterpret_cast<const uint4*>(&halo[ly_base]);
+    const uint32_t chi = c_eq >> 24;                    // Potts: high byte of the cutoff
+    const bool lo_matters = (c_eq & 0xFFFFFFu) != 0u;   // ties need the low 24 bits
 #pragma unroll
     for (int g = 0; g < RPW / 8; ++g) {
         const int ly0 = ly_base + g * 8;
@@ -285,25 +290,30 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             const bool ok = col_ok && (yb + k < L);
             const int s = sreg[r];
             const int sd = sreg[r + 1];
-            const int sr_next = __shfl_down(s, 1, 64);
-            const int sr = edge_lane ? halo[ly] : sr_next;
+            const int sr_next = __builtin_amdgcn_mov_dpp(s, 0x130, 0xF, 0xF, false);  // wave_shl:1, lane i <- i+1
+            const uint32_t hword = (r < 4) ? hv.x : (r < 8) ? hv.y : (r < 12) ? hv.z : hv.w;
+            const int sr = edge_lane ? static_cast<int>((hword >> (8 * (r & 3))) & 0xFFu) : sr_next;
             const uint32_t word = (k < 2) ? hi.w0 : (k < 4) ? hi.w1 : (k < 6) ? hi.w2 : hi.w3;
             const uint32_t hr = (k & 1) ? ((word >> 8) & 0xFFu) : (word >> 24);
             const uint32_t hd = (k & 1) ? (word & 0xFFu) : ((word >> 16) & 0xFFu);
-            uint32_t cr, cd;
+            uint64_t mr, md;
+            bool tr, td;
             if (kClock) {
-                cr = cut[s * q + sr];
-                cd = cut[s * q + sd];
+                const uint32_t cr = cut[s * q + sr];
+                const uint32_t cd = cut[s * q + sd];
+                mr = __ballot(ok && (hr < (cr >> 24)));
+                md = __ballot(ok && (hd < (cd >> 24)));
+                tr = ok && (hr == (cr >> 24)) && (cr & 0xFFFFFFu);
+                td = ok && (hd == (cd >> 24)) && (cd & 0xFFFFFFu);
             } else {
-                cr = (s == sr) ? c_eq : 0u;
-                cd = (s == sd) ? c_eq : 0u;
+                // Potts: a bond needs equal spins and a high byte below the cutoff's
+                const uint64_t okm = __ballot(ok);
+                const uint64_t er = __ballot(s == sr), ed = __ballot(s == sd);
+                mr = okm & er & __ballot(hr < chi);
+                md = okm & ed & __ballot(hd < chi);
+                tr = lo_matters && ok && (s == sr) && (hr == chi);
+                td = lo_matters && ok && (s == sd) && (hd == chi);
             }
-            const bool br = ok && (hr < (cr >> 24));
-            const bool bd = ok && (hd < (cd >> 24));
-            const bool tr = ok && (hr == (cr >> 24)) && (cr & 0xFFFFFFu);
-            const bool td = ok && (hd == (cd >> 24)) && (cd & 0xFFFFFFu);
-            const uint64_t mr = __ballot(br);
-            const uint64_t md = __ballot(bd);
             if (lane == 0) {
                 raw_r[ly] = mr;
                 raw_d[ly] = md;
