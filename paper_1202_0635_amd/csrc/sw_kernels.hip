@@ -36,8 +36,8 @@ __device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) {
 // path halving: a visited node is pointed at its grandparent.  A halving store
 // may overwrite a concurrent lowering of that node; the union that lowered it
 // continues with the node's previous parent, so no connection is lost.
-__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x) {
-    uint32_t p = lds_load(&P[x]);
+// p is P[x], already loaded by the caller.
+__device__ __forceinline__ uint32_t lds_find_from(uint32_t* P, uint32_t x, uint32_t p) {
     while (p != x) {
         const uint32_t gp = lds_load(&P[p]);
         if (gp == p) return p;
@@ -47,6 +47,8 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x) {
     }
     return x;
 }
+
+__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x) { return lds_find_from(P, x, lds_load(&P[x])); }
 
 // Join the sets of a and b: the larger root is lowered to the smaller with an
 // LDS atomic min; if that root had meanwhile been linked elsewhere, its old
@@ -394,8 +396,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             const int start = 63 - __clzll(~(ir << 1) & (~0ull >> (63 - lane)));
             if (start == lane) run_start_rows |= 1u << r;
             const uint32_t node = static_cast<uint32_t>(ly * kTileW + start);
+            // the label above is usually still a root: one load, and the
+            // find loop runs only where it is not
             uint32_t cand = kNone;
-            if (r > 0 && y0 + ly < L && ((raw_d[ly - 1] >> lane) & 1ull)) cand = lds_find(P, lab_prev);
+            if (r > 0 && y0 + ly < L && ((raw_d[ly - 1] >> lane) & 1ull)) {
+                const uint32_t p = lds_load(&P[lab_prev]);
+                cand = (p == lab_prev) ? p : lds_find_from(P, lab_prev, p);
+            }
             if (start == lane) my_slot[lane] = kNone;
             __builtin_amdgcn_wave_barrier();
             if (cand != kNone) atomicMin(&my_slot[start], cand);
@@ -404,7 +411,12 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             const uint32_t lab = (m == kNone) ? node : m;
             P[ly * kTileW + lane] = (start == lane) ? lab : node;
             __builtin_amdgcn_wave_barrier();
-            if (cand != kNone && cand != m) lds_union(P, cand, m);
+            // cand and m were roots when found (m < cand); link cand under m
+            // at once, and join its new parent too if it was linked meanwhile
+            if (cand != kNone && cand != m) {
+                const uint32_t old = __hip_atomic_fetch_min(&P[cand], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old != cand) lds_union(P, old, m);
+            }
             lab_prev = lab;
         }
     }
