@@ -440,9 +440,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         if ((run_start_rows >> r) & 1u) {
+            // usually the run's label is itself a root: two loads, no store
             const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
-            const uint32_t root = lds_find(P, self);
-            lds_store(&P[self], root);
+            const uint32_t p = lds_load(&P[self]);
+            if (p != self) {
+                const uint32_t gp = lds_load(&P[p]);
+                if (gp != p) lds_store(&P[self], lds_find_from(P, p, gp));
+            }
         }
     }
     __syncthreads();
