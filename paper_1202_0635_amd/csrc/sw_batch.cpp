@@ -68,7 +68,7 @@ namespace {
 
 const char* const kListNames[kNumLists] = {"kb_bond_local<potts>", "kb_bond_local<clock>", "kb_block_merge",
                                            "kb_border_merge",      "kb_flatten",           "kb_flip",
-                                           "kb_counts"};
+                                           "kb_counts",            "kb_count_sum"};
 
 int bfail(sw_batch* b, hipError_t e, const char* what) {
     if (b) b->sticky = true;

@@ -109,7 +109,7 @@ struct BatchLaunch {
 };
 hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint32_t row);
 
-enum KernelId { kKBondLocal = 0, kKBlockMerge = 1, kKBorderMerge = 2, kKFlatten = 3, kKFlip = 4, kKCounts = 5, kNumKernels = 6 };
+enum KernelId { kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
 }  // namespace swmc

@@ -535,22 +535,24 @@ __device__ __forceinline__ BorderBond border_bond(const SweepArgs& a, uint32_t g
 // its block root.  The nodes belong to this block only, so nothing here
 // races with another workgroup.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kHashSlots = 8192;   // >= 2x the most nodes: 2 ends x 2 (mt-1) mt 64 bonds at mt = 4
+constexpr int kHashBits = 13;
+constexpr uint32_t kHashSlots = 1u << kHashBits;  // >= 2x the most nodes: 2 ends x 2 (mt-1) mt 64 bonds at mt = 4
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 static_assert(kHashSlots >= 2u * 2u * 2u * 3u * 4u * 64u, "hash table sized for 4 x 4 tile blocks");
 
-__device__ __forceinline__ uint32_t hash_slot(uint32_t key) { return (key * 2654435761u) >> 19; }  // 13 bits
-
-// Slot of key in the table, inserting it if absent (linear probing; the
-// table is never more than 3/8 full, so a free slot is always reached).
+// Slot of key in a table of 2^kBits slots, inserting it if absent (linear
+// probing; the tables are sized so that they never fill, so a free slot is
+// always reached).
+template <int kBits>
 __device__ __forceinline__ uint32_t hash_insert(uint32_t* keys, uint32_t key) {
-    uint32_t s = hash_slot(key);
-    for (uint32_t n = 0; n < kHashSlots; ++n) {
+    constexpr uint32_t kSlots = 1u << kBits;
+    uint32_t s = (key * 2654435761u) >> (32 - kBits);
+    for (uint32_t n = 0; n < kSlots; ++n) {
         const uint32_t old = atomicCAS(&keys[s], kEmptyKey, key);
         if (old == kEmptyKey || old == key) return s;
-        s = (s + 1) & (kHashSlots - 1);
+        s = (s + 1) & (kSlots - 1);
     }
-    return kHashSlots;  // unreachable by the sizing above
+    return kSlots;  // unreachable: the table never fills
 }
 
 __device__ __forceinline__ uint32_t node_find(uint32_t* par, uint32_t x) {
@@ -614,8 +616,8 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
         else
             b = horizontal_border_bond(a, tya + (k - nv) / ncols, xa + (k - nv) % ncols);
         if (!b.active) continue;
-        ends[r][0] = hash_insert(keys, b.i);
-        ends[r][1] = hash_insert(keys, b.j);
+        ends[r][0] = hash_insert<kHashBits>(keys, b.i);
+        ends[r][1] = hash_insert<kHashBits>(keys, b.j);
     }
     __syncthreads();
 #pragma unroll
@@ -698,20 +700,27 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
 }
 
 // ---------------------------------------------------------------------------
-// Cluster flip, four sites per thread.
+// Cluster flip.  One 64 x 64 tile per workgroup; thread t takes 16
+// consecutive sites of row t/4.  The tile's label words are staged in LDS, and
+// every step of a path whose target lies in the tile reads LDS: an ordinary
+// site's label word names its tile-local root, which is in the tile.  A
+// tile-local root that was merged across tiles holds a link (after the
+// flatten, straight to its cluster root) that may leave the tile; such steps
+// read global memory.
 // ---------------------------------------------------------------------------
 template <bool kVerify>
 __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int ty) {
-    // One 64 x 64 tile per workgroup: thread t takes 16 consecutive sites of
-    // row t/4, so the tile-local root words its sites point to were just read
-    // by the same workgroup.
+    __shared__ uint32_t tl[kTileH * kTileW];
     if (!a.ctl->live) return;
     const int L = a.L;
-    const int y = ty * kTileH + static_cast<int>(threadIdx.x >> 2);
-    const int xs = tx * kTileW + static_cast<int>(threadIdx.x & 3) * 16;
-    if (y >= L || xs >= L) return;
-    const int nx = min(16, L - xs);
-    const uint32_t base = __umul24(y, L) + static_cast<uint32_t>(xs);
+    const int ly = static_cast<int>(threadIdx.x >> 2), lx = static_cast<int>(threadIdx.x & 3) * 16;
+    const int y = ty * kTileH + ly;
+    const int xs = tx * kTileW + lx;
+    const int nx = (y < L) ? max(0, min(16, L - xs)) : 0;
+    const uint32_t nrows = static_cast<uint32_t>(min(kTileH, L - ty * kTileH));
+    const uint32_t ncols = static_cast<uint32_t>(min(kTileW, L - tx * kTileW));
+    const uint32_t tile_base = __umul24(ty * kTileH, L) + static_cast<uint32_t>(tx * kTileW);
+    const uint32_t base = __umul24(min(y, L - 1), L) + static_cast<uint32_t>(min(xs, L - 1));
     const bool full = (nx == 16) && ((base & 3u) == 0);
     uint32_t x[16], w[16];
     if (full) {
@@ -725,8 +734,33 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
         for (int k = 0; k < 16; ++k) w[k] = (k < nx) ? a.labels[base + k] : kRootFlag;
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = base + k;
-    // follow the sixteen paths together (independent loads in flight)
+    for (int k = 0; k < 16; ++k) tl[ly * kTileW + lx + k] = w[k];
+    __syncthreads();
+    // First step.  A target lies in the tile when its offset d from the
+    // tile's first site is below nrows * L and d mod L is below the tile's
+    // width; its row d / L comes from a float reciprocal corrected to the
+    // exact quotient (such offsets stay below 2^22).
+    const float inv_l = 1.0f / static_cast<float>(L);
+    const uint32_t span = nrows * static_cast<uint32_t>(L);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        x[k] = base + k;
+        if (!(w[k] & kRootFlag)) {
+            x[k] = w[k];
+            const uint32_t d = w[k] - tile_base;
+            bool in_tile = d < span;
+            uint32_t r = 0, c = 0;
+            if (in_tile) {
+                r = static_cast<uint32_t>(static_cast<float>(d) * inv_l);
+                if (r * static_cast<uint32_t>(L) > d) r -= 1;
+                else if (d - r * static_cast<uint32_t>(L) >= static_cast<uint32_t>(L)) r += 1;
+                c = d - r * static_cast<uint32_t>(L);
+                in_tile = c < ncols;
+            }
+            w[k] = in_tile ? tl[r * kTileW + c] : a.labels[x[k]];
+        }
+    }
+    // Further steps (paths through merged roots), sixteen paths together.
     bool pending = true;
     while (pending) {
         pending = false;
@@ -738,15 +772,23 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
                 pending = true;
             }
     }
+    if (nx == 0) return;
     uint32_t out[16];
     if (a.model == 0) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) out[k] = w[k] & 0xFFu;
     } else {
         const int m = static_cast<int>(a.ctl->mirror);
+        uint32_t old[4] = {0u, 0u, 0u, 0u};  // the sixteen old spins, four to a word
+        if (full && (base & 15u) == 0) {
+            const uint4 v = *reinterpret_cast<const uint4*>(a.spins + base);
+            old[0] = v.x; old[1] = v.y; old[2] = v.z; old[3] = v.w;
+        } else {
+            for (int k = 0; k < nx; ++k) old[k >> 2] |= static_cast<uint32_t>(static_cast<uint8_t>(a.spins[base + k])) << (8 * (k & 3));
+        }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            int sp = (k < nx) ? a.spins[base + k] : 0;
+            int sp = static_cast<int>((old[k >> 2] >> (8 * (k & 3))) & 0xFFu);
             if (w[k] & 1u) {
                 sp = m - sp;
                 if (sp < 0) sp += a.q;
@@ -1005,7 +1047,7 @@ __global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
 __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    const int nbx = (a.tiles_x + a.merge_tiles - 1) / a.merge_tiles;
+    const int nbx = static_cast<int>(merge_blocks_x(a.tiles_x, a.merge_tiles));
     block_merge(a, static_cast<int>(local % nbx), static_cast<int>(local / nbx));
 }
 
@@ -1058,10 +1100,10 @@ hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_block_merge(const SweepArgs& a, hipStream_t s) {
-    if (a.merge_tiles <= 1) return hipSuccess;
-    const unsigned nbx = static_cast<unsigned>((a.tiles_x + a.merge_tiles - 1) / a.merge_tiles);
-    const unsigned nby = static_cast<unsigned>((a.tiles_y + a.merge_tiles - 1) / a.merge_tiles);
-    hipLaunchKernelGGL(k_block_merge, dim3(nbx, nby), dim3(kMergeThreads), 0, s, a);
+    const int mt = a.merge_tiles;
+    if (mt <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_block_merge, dim3(merge_blocks_x(a.tiles_x, mt), merge_blocks_x(a.tiles_y, mt)),
+                       dim3(kMergeThreads), 0, s, a);
     return hipGetLastError();
 }
 

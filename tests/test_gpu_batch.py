@@ -31,9 +31,9 @@ def swmc():
     return swmc
 
 
-@pytest.mark.parametrize("mt", [1, 2, 4])
-def test_schedule_does_not_change_results(swmc, orc, mt):
-    L, q = 300, 2
+@pytest.mark.parametrize("mt,L", [(1, 300), (2, 300), (4, 300), (4, 1100), (2, 1100)])
+def test_schedule_does_not_change_results(swmc, orc, mt, L):
+    q = 2
     _say(f"[schedule] L={L} merge_tiles={mt}")
     lat = swmc.Lattice(L, q, "potts", T=TC2, seed=41).set_schedule(mt)
     ch = orc.Chain(L, q, "potts", T=TC2, seed=41)
@@ -125,3 +125,22 @@ def test_batch_schedules_and_tune(swmc, orc):
     for r in range(len(specs)):
         assert np.array_equal(b.spins(r), ref.spins(r))
         assert b.measure(r)["t"] == 6
+
+
+def test_profiles_name_every_launch(swmc):
+    # per-launch timing with measurement: every kernel that ran is reported by name
+    _say("[profile] batch and single lattice")
+    b = swmc.Batch([(96, 3, "potts", TC3, 1.0, 1), (64, 6, "clock", 0.9, 1.0, 2)])
+    b.sweep(3, measure=True, profile=True)
+    prof = b.profile()
+    for name in ("kb_bond_local<potts>", "kb_bond_local<clock>", "kb_border_merge", "kb_flatten", "kb_flip",
+                 "kb_counts", "kb_count_sum"):
+        assert prof[name][0] == 3, (name, prof)
+        assert prof[name][1] > 0.0
+    b.close()
+    lat = swmc.Lattice(200, 2, "potts", T=TC2, seed=3)
+    lat.sweep(4, measure=True, profile=True)
+    prof = lat.profile()
+    for name in ("k_bond_local", "k_block_merge", "k_border_merge", "k_flatten", "k_flip", "k_counts"):
+        assert prof[name][0] == 4, (name, prof)
+    lat.close()
