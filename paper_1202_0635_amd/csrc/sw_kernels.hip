@@ -637,11 +637,25 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
 // device-wide lock-free union.  Thread g < nbx*L: right edge of the last tile
 // column of block column g / L; the rest: bottom edges of block rows.
 // ---------------------------------------------------------------------------
+// True in the lowest lane of the wave that wants a given key (ka, kb); the
+// other wanting lanes with the same key get false.  The loop runs once per
+// distinct key among the wanting lanes.
+__device__ __forceinline__ bool wave_first(bool want, uint32_t ka, uint32_t kb) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint64_t m = __ballot(want);
+    while (m) {
+        const int j = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        const uint32_t ja = __shfl(ka, j, 64), jb = __shfl(kb, j, 64);
+        if (want && lane > static_cast<uint32_t>(j) && ka == ja && kb == jb) want = false;
+        m &= __ballot(want) & ~((2ull << j) - 1ull);
+    }
+    return want;
+}
+
 // Neighbouring lanes take neighbouring sites of one border and mostly find
-// the same two roots; a lane whose pair of roots equals the previous lane's
-// leaves the union to that lane.  (Every link ever stored points to an
-// ancestor, so equal found roots mean equal sets; the first lane of a run of
-// equal pairs does the union.)
+// the same two roots: of the lanes of a wave that found the same pair of
+// roots only the lowest does the union.  (Every link ever stored points to an
+// ancestor, so equal found roots mean equal sets.)
 __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t gid) {
     if (!a.ctl->live) return;
     const BorderBond b = border_bond(a, gid, a.merge_tiles);
@@ -658,9 +672,7 @@ __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t 
             wb = tmp;
         }
     }
-    const uint32_t pa = __shfl_up(ra, 1, 64), pb = __shfl_up(rb, 1, 64);
-    const bool repeat = (threadIdx.x & 63) != 0 && pa == ra && pb == rb;
-    if (b.active && ra != rb && !repeat) g_union_roots(a.labels, ra, wa, rb, wb);
+    if (wave_first(b.active && ra != rb, ra, rb)) g_union_roots(a.labels, ra, wa, rb, wb);
 }
 
 // After the merge: every tile-local root at the end of a border bond that
@@ -692,6 +704,8 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
     if (block == 0 && threadIdx.x == 0) a.ctl->t += 1;
     const BorderBond b = border_bond(a, block * blockDim.x + threadIdx.x, 1);
     // a tile-local root that the previous lane also reaches is left to it
+    // (a wave holds many distinct roots here, so a full per-wave
+    // deduplication costs more than the repeated walks it saves)
     const uint32_t i = b.active ? b.i : kRootFlag, j = b.active ? b.j : kRootFlag;
     const uint32_t pi = __shfl_up(i, 1, 64), pj = __shfl_up(j, 1, 64);
     const bool first = (threadIdx.x & 63) == 0;
