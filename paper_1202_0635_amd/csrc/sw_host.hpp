@@ -26,9 +26,11 @@ size_t up(size_t v);
 
 struct Layout {
     size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, border_roots, border_bonds, ring, scratch_row, table,
-        total;
+        spins2, labels2, total;
 };
-Layout layout_of(const sw_lattice& p);
+// Arena layout; with_pair adds the second spin and label buffers that the
+// fused flip-and-bond kernel alternates with (single-lattice contexts).
+Layout layout_of(const sw_lattice& p, bool with_pair = false);
 
 struct Observables {
     double e = 0.0, m2 = 0.0;

@@ -61,7 +61,10 @@ struct Control {
 static_assert(sizeof(Control) == 64, "control block is one 64-byte line");
 
 struct SweepArgs {
-    int8_t* spins;        // [N]
+    int8_t* spins;        // [N] the state the bond kernel reads (and the fused kernel writes)
+    int8_t* flip_out;     // [N] where k_flip writes the new state (usually spins)
+    const uint32_t* labels_prev;  // fused kernel: the previous sweep's forest
+    const int8_t* spins_prev;     // fused kernel: the state before the previous sweep
     uint64_t* bond_r;     // [L][w64]: bit x%64 of word x/64 = right bond of (x,y)
     uint64_t* bond_d;     // [L][w64]: down bonds
     uint32_t* labels;     // [N] union-find forest with root words (kRootFlag)
@@ -81,6 +84,9 @@ struct SweepArgs {
 // Launch wrappers (defined in sw_kernels.hip).
 hipError_t launch_init(const SweepArgs& a, hipStream_t s);
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s);
+// The previous sweep's flip (from labels_prev, spins_prev) fused with this
+// sweep's bond kernel: writes the flipped state to spins, then as k_bond_local.
+hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s);
 hipError_t launch_block_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
@@ -109,7 +115,7 @@ struct BatchLaunch {
 };
 hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint32_t row);
 
-enum KernelId { kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kNumKernels };
+enum KernelId { kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kKFlipBond, kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
 }  // namespace swmc

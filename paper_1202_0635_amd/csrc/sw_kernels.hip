@@ -20,7 +20,8 @@
 
 namespace swmc {
 
-const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge", "k_border_merge", "k_flatten", "k_flip", "k_counts"};
+const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge", "k_border_merge", "k_flatten",
+                                               "k_flip",       "k_counts",      "k_flip_bond"};
 
 namespace {
 
@@ -203,6 +204,28 @@ __global__ void __launch_bounds__(256) k_init(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The previous sweep's flip of one site, for the fused kernel: the root word
+// of the site's cluster in the previous forest gives the new value (Potts) or
+// the reflection bit for the old value (clock, mirror m).
+// ---------------------------------------------------------------------------
+template <bool kClock>
+__device__ __forceinline__ int flipped(uint32_t root_word, int old, int m, int q) {
+    if (!kClock) return static_cast<int>(root_word & 0xFFu);
+    int v = old;
+    if (root_word & 1u) {
+        v = m - old;
+        if (v < 0) v += q;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t root_word_of(const uint32_t* lab, uint32_t i) {
+    uint32_t w = lab[i];
+    while (!(w & kRootFlag)) w = lab[w];
+    return w;
+}
+
+// ---------------------------------------------------------------------------
 // Bonds + tile-local labeling.  Lane = column; each wave owns kTileH/4
 // consecutive rows.  Each spin is loaded once: its right neighbour comes from
 // the next lane, its lower neighbour from the next row held in registers.
@@ -211,7 +234,7 @@ __global__ void __launch_bounds__(256) k_init(SweepArgs a) {
 // byte equals the cutoff's high byte (probability 2^-8), so those ties are
 // collected in a tile-wide list and resolved with one draw per tied site.
 // ---------------------------------------------------------------------------
-template <int kModel>
+template <int kModel, bool kFused>
 __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty) {
     constexpr bool kClock = kModel == 1;
     constexpr int RPW = kTileH / kWaves;  // rows per wave
@@ -256,20 +279,60 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->mirror = static_cast<uint32_t>(m);
     }
     if (threadIdx.x == 0) ntie = 0;
+    // Fused kernel: the spins this tile reads are the previous sweep's flip of
+    // the previous state (mirror of sweep t - 1 for the clock model).
+    const int m_prev = (kFused && kClock) ? mirror_of(t - 1, q, k0, k1) : 0;
     if (threadIdx.x < kTileH) {
         const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
         const int yh = y0 + static_cast<int>(threadIdx.x);
-        halo[threadIdx.x] = (yh < L) ? static_cast<uint8_t>(a.spins[__umul24(yh, L) + static_cast<uint32_t>(xh)]) : 0;
+        const uint32_t ih = __umul24(yh, L) + static_cast<uint32_t>(xh);
+        int v = 0;
+        if (yh < L) {
+            if (kFused)
+                v = flipped<kClock>(root_word_of(a.labels_prev, ih), kClock ? a.spins_prev[ih] : 0, m_prev, q);
+            else
+                v = a.spins[ih];
+        }
+        halo[threadIdx.x] = static_cast<uint8_t>(v);
     }
     __syncthreads();
 
     const int ly_base = wave * RPW;
     const int y_base = y0 + ly_base;
     int sreg[RPW + 1];
+    if (kFused) {
+        // the paths of the RPW + 1 sites of this lane are followed together
+        uint32_t w[RPW + 1];
 #pragma unroll
-    for (int r = 0; r <= RPW; ++r) {
-        const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
-        sreg[r] = (col_ok && yr <= L) ? a.spins[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : 0;
+        for (int r = 0; r <= RPW; ++r) {
+            const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
+            w[r] = (col_ok && yr <= L) ? a.labels_prev[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : kRootFlag;
+        }
+        bool pending = true;
+        while (pending) {
+            pending = false;
+#pragma unroll
+            for (int r = 0; r <= RPW; ++r)
+                if (!(w[r] & kRootFlag)) {
+                    w[r] = a.labels_prev[w[r]];
+                    pending = true;
+                }
+        }
+#pragma unroll
+        for (int r = 0; r <= RPW; ++r) {
+            const int yr = y_base + r;
+            const bool ok = col_ok && yr <= L;
+            const uint32_t i = __umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x);
+            sreg[r] = ok ? flipped<kClock>(w[r], kClock ? a.spins_prev[i] : 0, m_prev, q) : 0;
+            // the new state of this wave's own rows
+            if (r < RPW && col_ok && yr < L) a.spins[i] = static_cast<int8_t>(sreg[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r <= RPW; ++r) {
+            const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
+            sreg[r] = (col_ok && yr <= L) ? a.spins[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : 0;
+        }
     }
     const bool edge_lane = (lane == nvalid - 1);
 
@@ -337,14 +400,20 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t row = __umul24(y, L);
         const uint32_t i = row + static_cast<uint32_t>(xx);
         const Words4 lo = draw(i, t, kBondLo, k0, k1);
-        const int s = a.spins[i];
+        // (the fused kernel's spin buffer is being written by other
+        // workgroups, so its spins are recomputed from the previous forest)
+        auto spin_at = [&](uint32_t j) -> int {
+            if (kFused) return flipped<kClock>(root_word_of(a.labels_prev, j), kClock ? a.spins_prev[j] : 0, m_prev, q);
+            return a.spins[j];
+        };
+        const int s = kClock ? spin_at(i) : 0;  // a Potts tie implies equal spins
         if (e & (1u << 12)) {
-            const int sr = a.spins[row + static_cast<uint32_t>((xx + 1 == L) ? 0 : xx + 1)];
-            const uint32_t c = kClock ? cut[s * q + sr] : c_eq;  // a Potts tie implies equal spins
+            const int sr = kClock ? spin_at(row + static_cast<uint32_t>((xx + 1 == L) ? 0 : xx + 1)) : 0;
+            const uint32_t c = kClock ? cut[s * q + sr] : c_eq;
             if ((lo.w0 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_r[ly], 1ull << lx);
         }
         if (e & (1u << 13)) {
-            const int sd = a.spins[__umul24((y + 1 == L) ? 0 : y + 1, L) + static_cast<uint32_t>(xx)];
+            const int sd = kClock ? spin_at(__umul24((y + 1 == L) ? 0 : y + 1, L) + static_cast<uint32_t>(xx)) : 0;
             const uint32_t c = kClock ? cut[s * q + sd] : c_eq;
             if ((lo.w1 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_d[ly], 1ull << lx);
         }
@@ -813,7 +882,7 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
     if (full) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            *reinterpret_cast<uint32_t*>(a.spins + base + 4 * g) =
+            *reinterpret_cast<uint32_t*>(a.flip_out + base + 4 * g) =
                 out[4 * g] | (out[4 * g + 1] << 8) | (out[4 * g + 2] << 16) | (out[4 * g + 3] << 24);
             if (kVerify)
                 *reinterpret_cast<uint4*>(a.canon + base + 4 * g) = make_uint4(x[4 * g], x[4 * g + 1], x[4 * g + 2], x[4 * g + 3]);
@@ -822,7 +891,7 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
 #pragma unroll
         for (int k = 0; k < 16; ++k)
             if (k < nx) {
-                a.spins[base + k] = static_cast<int8_t>(out[k]);
+                a.flip_out[base + k] = static_cast<int8_t>(out[k]);
                 if (kVerify) a.canon[base + k] = x[k];
             }
     }
@@ -1018,7 +1087,13 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
 template <int kModel>
 __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_local_tile<kModel>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_local_tile<kModel, false>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+}
+
+template <int kModel>
+__global__ void __launch_bounds__(kBlock) k_flip_bond(SweepArgs a) {
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    bond_local_tile<kModel, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
@@ -1055,7 +1130,7 @@ template <int kModel>
 __global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    bond_local_tile<kModel>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+    bond_local_tile<kModel, false>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
@@ -1110,6 +1185,15 @@ hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_bond_local<1>, grid, dim3(kBlock), 0, s, a);
     else
         hipLaunchKernelGGL(k_bond_local<0>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
+    if (a.model == 1)
+        hipLaunchKernelGGL(k_flip_bond<1>, grid, dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_flip_bond<0>, grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ void build_table(const sw_lattice& p, uint32_t* out) {
 // ---------------------------------------------------------------------------
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-Layout layout_of(const sw_lattice& p) {
+Layout layout_of(const sw_lattice& p, bool with_pair) {
     const size_t L = static_cast<size_t>(p.L);
     const size_t N = L * L;
     const size_t w64 = (L + 63) / 64;
@@ -124,6 +124,10 @@ Layout layout_of(const sw_lattice& p) {
     l.ring = o; o += up(static_cast<size_t>(kRing) * kRowWords * 8);
     l.scratch_row = o; o += up(kRowWords * 8);
     l.table = o; o += up(table_entries(p) * 4);
+    if (with_pair) {
+        l.spins2 = o; o += up(N);
+        l.labels2 = o; o += up(N * 4);
+    }
     l.total = o;
     return l;
 }
@@ -176,6 +180,7 @@ uint32_t blocks_for(int l, const SweepArgs& a) {
 SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     SweepArgs a{};
     a.spins = reinterpret_cast<int8_t*>(base + lay.spins);
+    a.flip_out = a.spins;
     a.bond_r = reinterpret_cast<uint64_t*>(base + lay.bond_r);
     a.bond_d = reinterpret_cast<uint64_t*>(base + lay.bond_d);
     a.labels = reinterpret_cast<uint32_t*>(base + lay.labels);
@@ -317,7 +322,7 @@ size_t sw_state_bytes(const sw_lattice* p) {
         fail(SW_EINVAL, "%s", why.c_str());
         return 0;
     }
-    return layout_of(*p).total;
+    return layout_of(*p, true).total;
 }
 
 int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n) {
@@ -333,7 +338,7 @@ int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_c
     *out = nullptr;
     std::string why;
     if (!lattice_ok(p, &why)) return fail(SW_EINVAL, "%s", why.c_str());
-    const Layout lay = layout_of(*p);
+    const Layout lay = layout_of(*p, true);
     if (dev_mem) {
         if (reinterpret_cast<uintptr_t>(dev_mem) % kAlign != 0) return fail(SW_EINVAL, "dev_mem must be 256-byte aligned");
         if (bytes < lay.total) return fail(SW_ENOMEM, "dev_mem has %zu bytes, need %zu", bytes, lay.total);
@@ -403,29 +408,60 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         rows = 0;
         return st2;
     };
-    for (int32_t s = 0; s < nsweeps; ++s) {
-        const bool verify = (flags & SW_VERIFY) && (s == nsweeps - 1);
-        st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(c->args, c->stream); });
+    // Sweeps after the first of a call fuse the previous sweep's flip into
+    // their bond kernel: spins and labels alternate between the context's two
+    // buffers, and the call ends with a flip into the primary spin buffer.
+    int8_t* const spins0 = c->args.spins;
+    int8_t* const spins1 = reinterpret_cast<int8_t*>(c->base + c->lay.spins2);
+    uint32_t* const labels0 = c->args.labels;
+    uint32_t* const labels1 = reinterpret_cast<uint32_t*>(c->base + c->lay.labels2);
+    auto count_state = [&](SweepArgs a) -> int {
+        st = next_row(&a.count_row);
         if (st) return st;
-        if (c->args.merge_tiles > 1) {
-            st = timed(c, profile, kKBlockMerge, [&] { return launch_block_merge(c->args, c->stream); });
+        st = timed(c, profile, kKCounts, [&] { return launch_counts(a, c->stream); });
+        if (st) return st;
+        return row_done();
+    };
+    SweepArgs a = c->args;
+    for (int32_t s = 0; s < nsweeps; ++s) {
+        const bool last = s == nsweeps - 1;
+        const bool verify = (flags & SW_VERIFY) && last;
+        if (s == 0) {
+            st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(a, c->stream); });
+            if (st) return st;
+        } else {
+            SweepArgs f = a;
+            f.labels_prev = a.labels;
+            f.spins_prev = a.spins;
+            f.labels = (a.labels == labels0) ? labels1 : labels0;
+            f.spins = (a.spins == spins0) ? spins1 : spins0;
+            st = timed(c, profile, kKFlipBond, [&] { return launch_flip_bond(f, c->stream); });
+            if (st) return st;
+            a = f;
+            if (measure) {  // the state after sweep s - 1, which the fused kernel wrote
+                st = count_state(a);
+                if (st) return st;
+            }
+        }
+        if (a.merge_tiles > 1) {
+            st = timed(c, profile, kKBlockMerge, [&] { return launch_block_merge(a, c->stream); });
             if (st) return st;
         }
-        st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(c->args, c->stream); });
+        st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(a, c->stream); });
         if (st) return st;
-        st = timed(c, profile, kKFlatten, [&] { return launch_flatten(c->args, c->stream); });
+        st = timed(c, profile, kKFlatten, [&] { return launch_flatten(a, c->stream); });
         if (st) return st;
-        st = timed(c, profile, kKFlip, [&] { return launch_flip(c->args, verify, c->stream); });
-        if (st) return st;
-        if (verify) c->have_canon = true;
-        if (measure) {
-            SweepArgs a = c->args;
-            st = next_row(&a.count_row);
+        if (last) {
+            SweepArgs f = a;
+            f.flip_out = spins0;
+            st = timed(c, profile, kKFlip, [&] { return launch_flip(f, verify, c->stream); });
             if (st) return st;
-            st = timed(c, profile, kKCounts, [&] { return launch_counts(a, c->stream); });
-            if (st) return st;
-            st = row_done();
-            if (st) return st;
+            if (verify) c->have_canon = true;
+            if (measure) {
+                f.spins = spins0;
+                st = count_state(f);
+                if (st) return st;
+            }
         }
     }
     return flush_ring(c, rows);

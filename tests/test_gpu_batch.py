@@ -141,6 +141,9 @@ def test_profiles_name_every_launch(swmc):
     lat = swmc.Lattice(200, 2, "potts", T=TC2, seed=3)
     lat.sweep(4, measure=True, profile=True)
     prof = lat.profile()
-    for name in ("k_bond_local", "k_block_merge", "k_border_merge", "k_flatten", "k_flip", "k_counts"):
-        assert prof[name][0] == 4, (name, prof)
+    # a call: one bond kernel, then the fused flip-and-bond kernel, one final flip
+    expect = {"k_bond_local": 1, "k_flip_bond": 3, "k_block_merge": 4, "k_border_merge": 4, "k_flatten": 4,
+              "k_flip": 1, "k_counts": 4}
+    for name, n in expect.items():
+        assert prof[name][0] == n, (name, prof)
     lat.close()

@@ -86,6 +86,30 @@ def test_parity_from_arbitrary_state(swmc, orc, L, q, model, T):
         lat.close()
 
 
+# Several sweeps in one call run the previous sweep's flip inside the next
+# sweep's bond kernel (alternating spin and label buffers); the state after
+# every call, and the last sweep's labels, must be the oracle's.
+@pytest.mark.parametrize("L,q,model,T,seed,calls", [
+    (2, 2, "potts", TC2, 5, (4, 3)), (3, 3, "potts", 0.7, 9, (5,)), (5, 6, "clock", 0.6, 4, (2, 1, 3)),
+    (64, 2, "potts", TC2, 1, (6,)), (70, 2, "clock", 1.2, 12, (3, 2)), (100, 3, "potts", TC3, 7, (5,)),
+    (130, 6, "clock", 0.9, 3, (4, 1)), (127, 2, "potts", 0.5, 13, (4,)), (200, 2, "potts", 5.0, 14, (3,)),
+    (192, 32, "potts", 0.4, 15, (3,)), (97, 32, "clock", 0.05, 16, (3,)),
+])
+def test_multi_sweep_calls(swmc, orc, L, q, model, T, seed, calls):
+    _say(f"[fused] L={L} q={q} {model} calls={calls}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=seed)
+    ch = orc.Chain(L, q, model, T=T, seed=seed)
+    for n in calls:
+        lat.sweep(n, verify=True)
+        ch.sweep(n)
+        br, bd = lat.bonds()  # the last sweep's bonds (from the fused kernel when n > 1)
+        assert np.array_equal(br.reshape(-1), ch.bond_r) and np.array_equal(bd.reshape(-1), ch.bond_d)
+        assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+        assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+    assert lat.measure()["t"] == sum(calls)
+    lat.close()
+
+
 def test_many_sweeps_batch_call(swmc, orc):
     # 40 sweeps enqueued by one call; compare the end state and last labels.
     L, q, T = 160, 2, TC2
