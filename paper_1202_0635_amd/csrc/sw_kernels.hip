@@ -282,42 +282,38 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // Fused kernel: the spins this tile reads are the previous sweep's flip of
     // the previous state (mirror of sweep t - 1 for the clock model).
     const int m_prev = (kFused && kClock) ? mirror_of(t - 1, q, k0, k1) : 0;
-    if (threadIdx.x < kTileH) {
-        const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
-        const int yh = y0 + static_cast<int>(threadIdx.x);
-        const uint32_t ih = __umul24(yh, L) + static_cast<uint32_t>(xh);
-        int v = 0;
-        if (yh < L) {
-            if (kFused)
-                v = flipped<kClock>(root_word_of(a.labels_prev, ih), kClock ? a.spins_prev[ih] : 0, m_prev, q);
-            else
-                v = a.spins[ih];
-        }
-        halo[threadIdx.x] = static_cast<uint8_t>(v);
-    }
-    __syncthreads();
+    // the column right of the tile: one site per lane of wave 0
+    const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
+    const int yh = y0 + lane;
+    const bool halo_lane = wave == 0 && yh < L;
+    const uint32_t ih = __umul24(min(yh, L - 1), L) + static_cast<uint32_t>(xh);
+    if (!kFused && wave == 0) halo[lane] = halo_lane ? static_cast<uint8_t>(a.spins[ih]) : 0;
 
     const int ly_base = wave * RPW;
     const int y_base = y0 + ly_base;
     int sreg[RPW + 1];
     if (kFused) {
-        // the paths of the RPW + 1 sites of this lane are followed together
-        uint32_t w[RPW + 1];
+        // the paths of the RPW + 1 sites of this lane (and of its halo site
+        // in wave 0) are followed together
+        uint32_t w[RPW + 2];
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
             const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
             w[r] = (col_ok && yr <= L) ? a.labels_prev[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : kRootFlag;
         }
+        w[RPW + 1] = halo_lane ? a.labels_prev[ih] : kRootFlag;
         bool pending = true;
         while (pending) {
             pending = false;
 #pragma unroll
-            for (int r = 0; r <= RPW; ++r)
+            for (int r = 0; r <= RPW + 1; ++r)
                 if (!(w[r] & kRootFlag)) {
                     w[r] = a.labels_prev[w[r]];
                     pending = true;
                 }
         }
+        if (wave == 0)
+            halo[lane] = halo_lane ? static_cast<uint8_t>(flipped<kClock>(w[RPW + 1], kClock ? a.spins_prev[ih] : 0, m_prev, q)) : 0;
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
             const int yr = y_base + r;
@@ -334,6 +330,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             sreg[r] = (col_ok && yr <= L) ? a.spins[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : 0;
         }
     }
+    __syncthreads();  // halo and cutoffs in LDS
     const bool edge_lane = (lane == nvalid - 1);
 
     // Phase 1: decisions on the high bytes; ties go to the list.  The right
@@ -1090,10 +1087,16 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     bond_local_tile<kModel, false>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-template <int kModel>
-__global__ void __launch_bounds__(kBlock) k_flip_bond(SweepArgs a) {
+// Potts: eight waves per SIMD (the scalar registers over the limit spill to
+// vector lanes); the clock kernel's occupancy is bounded by its LDS anyway.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_local_tile<kModel, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_local_tile<0, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+}
+
+__global__ void __launch_bounds__(kBlock) k_flip_bond_clock(SweepArgs a) {
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    bond_local_tile<1, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
@@ -1191,9 +1194,9 @@ hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
 hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
     if (a.model == 1)
-        hipLaunchKernelGGL(k_flip_bond<1>, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flip_bond_clock, grid, dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_flip_bond<0>, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flip_bond_potts, grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
