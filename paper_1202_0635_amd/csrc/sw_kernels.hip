@@ -242,7 +242,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     __shared__ uint32_t P[kTileH * kTileW];  // tie list, then the tile forest, then root lists
     __shared__ uint64_t raw_r[kTileH];       // right-bond masks of the tile's rows
     __shared__ uint64_t raw_d[kTileH];       // down-bond masks
-    __shared__ uint32_t cut[kClock ? 32 * 32 : 1];
+    extern __shared__ uint32_t cut[];         // clock: the q x q cutoff slice (sized at launch)
     __shared__ uint8_t halo[kTileH];         // spins of the column right of the tile
     __shared__ uint32_t slot[kWaves][kTileW];  // per-run minimum of the labelling pass
     __shared__ uint32_t ntie;
@@ -1087,14 +1087,14 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     bond_local_tile<kModel, false>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-// Potts: eight waves per SIMD (the scalar registers over the limit spill to
-// vector lanes); the clock kernel's occupancy is bounded by its LDS anyway.
+// Eight waves per SIMD (the scalar registers over the limit spill to vector
+// lanes).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     bond_local_tile<0, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-__global__ void __launch_bounds__(kBlock) k_flip_bond_clock(SweepArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_clock(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     bond_local_tile<1, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
@@ -1176,6 +1176,9 @@ __global__ void __launch_bounds__(kCountSumThreads) kb_count_sum(BatchMap m, uin
 
 }  // namespace
 
+// Dynamic LDS of the clock bond kernels: the q x q cutoff slice.
+size_t cut_bytes(int q) { return static_cast<size_t>(q) * q * sizeof(uint32_t); }
+
 hipError_t launch_init(const SweepArgs& a, hipStream_t s) {
     const size_t N = static_cast<size_t>(a.L) * a.L;
     hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>((N + 255) / 256)), dim3(256), 0, s, a);
@@ -1185,7 +1188,7 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t s) {
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
     if (a.model == 1)
-        hipLaunchKernelGGL(k_bond_local<1>, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_bond_local<1>, grid, dim3(kBlock), cut_bytes(a.q), s, a);
     else
         hipLaunchKernelGGL(k_bond_local<0>, grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
@@ -1194,7 +1197,7 @@ hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
 hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
     if (a.model == 1)
-        hipLaunchKernelGGL(k_flip_bond_clock, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_flip_bond_clock, grid, dim3(kBlock), cut_bytes(a.q), s, a);
     else
         hipLaunchKernelGGL(k_flip_bond_potts, grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
@@ -1247,7 +1250,7 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
     const dim3 grid(l.blocks);
     switch (k) {
         case kBKBondPotts: hipLaunchKernelGGL(kb_bond_local<0>, grid, dim3(kBlock), 0, s, m); break;
-        case kBKBondClock: hipLaunchKernelGGL(kb_bond_local<1>, grid, dim3(kBlock), 0, s, m); break;
+        case kBKBondClock: hipLaunchKernelGGL(kb_bond_local<1>, grid, dim3(kBlock), cut_bytes(32), s, m); break;
         case kBKBlockMerge: hipLaunchKernelGGL(kb_block_merge, grid, dim3(kMergeThreads), 0, s, m); break;
         case kBKBorderMerge: hipLaunchKernelGGL(kb_border_merge, grid, dim3(256), 0, s, m); break;
         case kBKFlatten: hipLaunchKernelGGL(kb_flatten, grid, dim3(256), 0, s, m); break;
