@@ -61,8 +61,10 @@ def lib() -> ctypes.CDLL:
             "or_init": (None, [c_int, c_int, c_u64, i8p]),
             "or_mirror": (c_int, [c_int, c_u64, c_u64]),
             "or_bonds": (None, [c_int, c_int, c_int, u32p, c_u64, c_u64, i8p, u8p, u8p]),
+            "or_bonds_at": (None, [c_int, c_int, c_int, u32p, c_u64, c_u64, i8p, c_i64, i64p, u8p, u8p]),
             "or_label": (None, [c_int, u8p, u8p, i32p]),
             "or_flip": (None, [c_int, c_int, c_int, c_u64, c_u64, i32p, i8p]),
+            "or_flip_at": (None, [c_int, c_int, c_u64, c_u64, c_i64, i32p, i8p, i8p]),
             "or_sweep": (c_i64, [c_int, c_int, c_int, u32p, c_u64, c_u64, i8p, u8p, u8p, i32p]),
             "or_counts": (None, [c_int, c_int, i8p, i64p, i64p]),
             "or_observables": (None, [c_int, c_int, c_int, c_dbl, i64p, i64p, f64p, f64p]),
@@ -140,6 +142,18 @@ def bonds(L, q, model, table, seed, t, spins):
     return br.reshape(L, L), bd.reshape(L, L)
 
 
+def bonds_at(L, q, model, table, seed, t, spins, sites):
+    """Bonds owned by the given row-major sites (Sec. 2 steps (i)-(iii)), from the whole state."""
+    s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
+    assert s.size == L * L
+    idx = np.ascontiguousarray(sites, dtype=np.int64).reshape(-1)
+    br = np.zeros(idx.size, dtype=np.uint8)
+    bd = np.zeros(idx.size, dtype=np.uint8)
+    lib().or_bonds_at(L, q, model_id(model), _p(table, ctypes.c_uint32), seed, t, _p(s, ctypes.c_int8),
+                      idx.size, _p(idx, ctypes.c_int64), _p(br, ctypes.c_uint8), _p(bd, ctypes.c_uint8))
+    return br, bd
+
+
 def label(L, bond_r, bond_d) -> np.ndarray:
     br = np.ascontiguousarray(bond_r, dtype=np.uint8).reshape(-1)
     bd = np.ascontiguousarray(bond_d, dtype=np.uint8).reshape(-1)
@@ -153,6 +167,17 @@ def flip(L, q, model, seed, t, labels, spins) -> np.ndarray:
     lab = np.ascontiguousarray(labels, dtype=np.int32).reshape(-1)
     lib().or_flip(L, q, model_id(model), seed, t, _p(lab, ctypes.c_int32), _p(s, ctypes.c_int8))
     return s.reshape(L, L)
+
+
+def flip_at(q, model, seed, t, roots, old):
+    """New values of single sites (Sec. 2 steps (v)-(vii)): site k belongs to
+    the cluster whose canonical label is roots[k] and had value old[k]."""
+    r = np.ascontiguousarray(roots, dtype=np.int32).reshape(-1)
+    o = np.ascontiguousarray(old, dtype=np.int8).reshape(-1)
+    out = np.zeros(r.size, dtype=np.int8)
+    lib().or_flip_at(q, model_id(model), seed, t, r.size, _p(r, ctypes.c_int32), _p(o, ctypes.c_int8),
+                     _p(out, ctypes.c_int8))
+    return out
 
 
 class Chain:

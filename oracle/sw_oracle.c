@@ -200,29 +200,48 @@ int or_mirror(int q, uint64_t seed, uint64_t t) {
 /* ------------------------------------------------------------------ */
 /* Step 1: active bonds, Sec. 2 steps (i)-(iii).                            */
 /* ------------------------------------------------------------------ */
+/* The two bonds owned by site (y, x): to its right and to its lower
+ * neighbour.  C is the cutoff slice of this sweep (R2, R3). */
+static void bond_site(int L, int q, const uint32_t* C, uint64_t seed, uint64_t t, const int8_t* spins,
+                      int y, int x, uint8_t* br, uint8_t* bd) {
+    int64_t i = (int64_t)y * L + x;
+    int64_t j_right = (int64_t)y * L + (x + 1) % L;
+    int64_t j_down = (int64_t)((y + 1) % L) * L + x;
+    uint32_t w_hi[4], w_lo[4];
+    or_draw(seed, (uint32_t)((int64_t)(y / 8) * L + x), t, OR_P_BOND_HI, w_hi);
+    or_draw(seed, (uint32_t)i, t, OR_P_BOND_LO, w_lo);
+    uint32_t word = w_hi[(y % 8) / 2];
+    int shift = (y % 2 == 0) ? 16 : 0; /* this row's two bytes */
+    uint32_t hi_right = (word >> (shift + 8)) & 0xFFu;
+    uint32_t hi_down = (word >> shift) & 0xFFu;
+    uint32_t u_right = (hi_right << 24) | (w_lo[0] & 0x00FFFFFFu);
+    uint32_t u_down = (hi_down << 24) | (w_lo[1] & 0x00FFFFFFu);
+    int a = spins[i];
+    *br = (uint8_t)(u_right < C[a * q + spins[j_right]]);
+    *bd = (uint8_t)(u_down < C[a * q + spins[j_down]]);
+}
+
+static const uint32_t* cutoff_slice(int q, int model, const uint32_t* table, uint64_t seed, uint64_t t) {
+    int m = (model == OR_CLOCK) ? or_mirror(q, seed, t) : 0;
+    return (model == OR_CLOCK) ? table + (size_t)m * q * q : table;
+}
+
 void or_bonds(int L, int q, int model, const uint32_t* table, uint64_t seed, uint64_t t,
               const int8_t* spins, uint8_t* bond_r, uint8_t* bond_d) {
-    int m = (model == OR_CLOCK) ? or_mirror(q, seed, t) : 0;
-    const uint32_t* C = (model == OR_CLOCK) ? table + (size_t)m * q * q : table;
+    const uint32_t* C = cutoff_slice(q, model, table, seed, t);
     for (int y = 0; y < L; ++y) {
         for (int x = 0; x < L; ++x) {
             int64_t i = (int64_t)y * L + x;
-            int64_t j_right = (int64_t)y * L + (x + 1) % L;
-            int64_t j_down = (int64_t)((y + 1) % L) * L + x;
-            uint32_t w_hi[4], w_lo[4];
-            or_draw(seed, (uint32_t)((int64_t)(y / 8) * L + x), t, OR_P_BOND_HI, w_hi);
-            or_draw(seed, (uint32_t)i, t, OR_P_BOND_LO, w_lo);
-            uint32_t word = w_hi[(y % 8) / 2];
-            int shift = (y % 2 == 0) ? 16 : 0; /* this row's two bytes */
-            uint32_t hi_right = (word >> (shift + 8)) & 0xFFu;
-            uint32_t hi_down = (word >> shift) & 0xFFu;
-            uint32_t u_right = (hi_right << 24) | (w_lo[0] & 0x00FFFFFFu);
-            uint32_t u_down = (hi_down << 24) | (w_lo[1] & 0x00FFFFFFu);
-            int a = spins[i];
-            bond_r[i] = (uint8_t)(u_right < C[a * q + spins[j_right]]);
-            bond_d[i] = (uint8_t)(u_down < C[a * q + spins[j_down]]);
+            bond_site(L, q, C, seed, t, spins, y, x, &bond_r[i], &bond_d[i]);
         }
     }
+}
+
+void or_bonds_at(int L, int q, int model, const uint32_t* table, uint64_t seed, uint64_t t,
+                 const int8_t* spins, int64_t n, const int64_t* sites, uint8_t* bond_r, uint8_t* bond_d) {
+    const uint32_t* C = cutoff_slice(q, model, table, seed, t);
+    for (int64_t k = 0; k < n; ++k)
+        bond_site(L, q, C, seed, t, spins, (int)(sites[k] / L), (int)(sites[k] % L), &bond_r[k], &bond_d[k]);
 }
 
 /* ------------------------------------------------------------------ */
@@ -282,6 +301,13 @@ void or_label(int L, const uint8_t* bond_r, const uint8_t* bond_d, int32_t* labe
 /* ------------------------------------------------------------------ */
 /* Step 3: spin flip, Sec. 2 steps (v)-(vii) (R6).                          */
 /* ------------------------------------------------------------------ */
+/* New value of a site with old value s in a cluster whose draw is W. */
+static int8_t flip_value(int q, int model, int m, uint32_t W, int8_t s) {
+    if (model == OR_POTTS) return (int8_t)or_qmap(W, (uint32_t)q);
+    if (W >= 0x80000000u) return (int8_t)(((m - s) % q + q) % q);
+    return s;
+}
+
 void or_flip(int L, int q, int model, uint64_t seed, uint64_t t, const int32_t* label,
              int8_t* spins) {
     int64_t N = (int64_t)L * L;
@@ -295,15 +321,18 @@ void or_flip(int L, int q, int model, uint64_t seed, uint64_t t, const int32_t* 
             cluster_word[i] = w[0];
         }
     }
-    for (int64_t i = 0; i < N; ++i) {
-        uint32_t W = cluster_word[label[i]];
-        if (model == OR_POTTS) {
-            spins[i] = (int8_t)or_qmap(W, (uint32_t)q);
-        } else if (W >= 0x80000000u) {
-            spins[i] = (int8_t)(((m - spins[i]) % q + q) % q);
-        }
-    }
+    for (int64_t i = 0; i < N; ++i) spins[i] = flip_value(q, model, m, cluster_word[label[i]], spins[i]);
     free(cluster_word);
+}
+
+void or_flip_at(int q, int model, uint64_t seed, uint64_t t, int64_t n, const int32_t* root,
+                const int8_t* old, int8_t* out) {
+    int m = (model == OR_CLOCK) ? or_mirror(q, seed, t) : 0;
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t w[4];
+        or_draw(seed, (uint32_t)root[k], t, OR_P_CLUSTER, w);
+        out[k] = flip_value(q, model, m, w[0], old[k]);
+    }
 }
 
 int64_t or_sweep(int L, int q, int model, const uint32_t* table, uint64_t seed, uint64_t t,

@@ -58,9 +58,17 @@ void or_init(int L, int q, uint64_t seed, int8_t* spins);
 int or_mirror(int q, uint64_t seed, uint64_t t);
 void or_bonds(int L, int q, int model, const uint32_t* table, uint64_t seed, uint64_t t,
               const int8_t* spins, uint8_t* bond_r, uint8_t* bond_d);
+/* The bonds owned by the n sites sites[k] (row-major indices), from the
+ * whole state spins: bond_r[k], bond_d[k]. */
+void or_bonds_at(int L, int q, int model, const uint32_t* table, uint64_t seed, uint64_t t,
+                 const int8_t* spins, int64_t n, const int64_t* sites, uint8_t* bond_r, uint8_t* bond_d);
 void or_label(int L, const uint8_t* bond_r, const uint8_t* bond_d, int32_t* label);
 void or_flip(int L, int q, int model, uint64_t seed, uint64_t t, const int32_t* label,
              int8_t* spins);
+/* The flip of n single sites: site k has canonical label root[k] and old
+ * value old[k]; out[k] receives its new value. */
+void or_flip_at(int q, int model, uint64_t seed, uint64_t t, int64_t n, const int32_t* root,
+                const int8_t* old, int8_t* out);
 /* One full sweep t: bonds, labels, flip.  label (N int32) receives the
  * canonical labels; bond_r/bond_d (N uint8) the bonds.  Returns the number of
  * clusters. */

@@ -173,6 +173,32 @@ def test_full_size_L4096(swmc, orc, model, q, T, nsw):
     lat.close()
 
 
+@pytest.mark.parametrize("model,q,T", [("potts", 2, TC2), ("clock", 6, 0.9)])
+def test_full_size_L4096_one_call(swmc, orc, model, q, T):
+    # The benchmark's launch configuration: several sweeps in one call, every
+    # sweep after the first running the fused flip-and-bond kernel.  Whole
+    # states are compared, with the counts of a measured call and the bonds and
+    # canonical labels of a verified one.
+    L = 4096
+    _say(f"[full, one call] L=4096 {model} q={q}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=2)
+    ch = orc.Chain(L, q, model, T=T, seed=2)
+    lat.sweep(3, measure=True)
+    ch.sweep(3)
+    assert np.array_equal(lat.spins().reshape(-1), ch.spins), "spins differ after a 3-sweep call"
+    ob = lat.measure()
+    hist, pair = ch.counts()
+    assert ob["t"] == 3 and ob["samples"] == 3
+    assert np.array_equal(ob["hist"], hist) and np.array_equal(ob["pair_hist"], pair)
+    lat.sweep(2, verify=True)
+    ch.sweep(2)
+    br, bd = lat.bonds()
+    assert np.array_equal(br.reshape(-1), ch.bond_r) and np.array_equal(bd.reshape(-1), ch.bond_d)
+    assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+    assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+    lat.close()
+
+
 def test_invalid_arguments_raise(swmc):
     with pytest.raises(swmc.SwError):
         swmc.Lattice(1, 2, "potts", T=1.0)

@@ -173,3 +173,20 @@ def test_counts_and_energy_identities(orc):
             M2 = np.cos(th).sum() ** 2 + np.sin(th).sum() ** 2
         assert abs(e - H / (L * L)) < 1e-12
         assert abs(m2 - M2 / (L * L) ** 2) < 1e-12
+
+
+@pytest.mark.parametrize("model,q,T", [("potts", 3, 0.9), ("clock", 6, 0.9), ("potts", 2, 1.1)])
+def test_single_site_entry_points_match_whole_lattice(orc, model, q, T):
+    # The single-site bond and flip entry points (used to check sampled sites
+    # of lattices too large for a whole oracle sweep) give the whole-lattice
+    # functions' results at every site of a ragged lattice, in shuffled order.
+    L, seed, t = 37, 5, 3
+    tab = orc.cutoffs(model, q, T)
+    s = orc.init(L, q, seed)
+    br, bd = orc.bonds(L, q, model, tab, seed, t, s)
+    idx = np.random.default_rng(1).permutation(L * L)
+    b2, d2 = orc.bonds_at(L, q, model, tab, seed, t, s, idx)
+    assert np.array_equal(br.reshape(-1)[idx], b2) and np.array_equal(bd.reshape(-1)[idx], d2)
+    lab = orc.label(L, br, bd).reshape(-1)
+    f = orc.flip(L, q, model, seed, t, lab, s).reshape(-1)
+    assert np.array_equal(f[idx], orc.flip_at(q, model, seed, t, lab[idx], s.reshape(-1)[idx]))
