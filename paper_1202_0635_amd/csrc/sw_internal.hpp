@@ -78,6 +78,9 @@ struct SweepArgs {
     int L, q, model, w64;
     int tiles_x, tiles_y;
     int merge_tiles;      // tiles per side of a first-level merge block (1: no block level)
+    int root_copies;      // k_flatten stores the cluster's root word (not a link) at every linked
+                          // tile-local root: the labels then lead to a root word in at most two
+                          // loads, but no longer name the root site (off in verify mode)
     uint32_t key0, key1;
 };
 

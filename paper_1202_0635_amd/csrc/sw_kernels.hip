@@ -234,21 +234,35 @@ __device__ __forceinline__ uint32_t root_word_of(const uint32_t* lab, uint32_t i
 // byte equals the cutoff's high byte (probability 2^-8), so those ties are
 // collected in a tile-wide list and resolved with one draw per tied site.
 // ---------------------------------------------------------------------------
-template <int kModel, bool kFused>
-__device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty) {
+struct BondShared {
+    uint32_t P[kTileH * kTileW];          // tie list, then the tile forest, then root lists
+    uint64_t raw_r[kTileH];               // right-bond masks of the tile's rows
+    uint64_t raw_d[kTileH];               // down-bond masks
+    alignas(16) uint8_t halo[kTileH];     // spins of the column right of the tile
+    uint32_t slot[kWaves][kTileW];        // per-run minimum of the labelling pass
+    uint32_t ntie;
+};
+
+// kFull: the tile lies inside the lattice (no column or row beyond L), which
+// removes the bounds tests from every row.
+template <int kModel, bool kFused, bool kFull>
+__device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty, BondShared& sh) {
     constexpr bool kClock = kModel == 1;
     constexpr int RPW = kTileH / kWaves;  // rows per wave
     static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
-    __shared__ uint32_t P[kTileH * kTileW];  // tie list, then the tile forest, then root lists
-    __shared__ uint64_t raw_r[kTileH];       // right-bond masks of the tile's rows
-    __shared__ uint64_t raw_d[kTileH];       // down-bond masks
-    extern __shared__ uint32_t cut[];         // clock: the q x q cutoff slice (sized at launch)
-    __shared__ uint8_t halo[kTileH];         // spins of the column right of the tile
-    __shared__ uint32_t slot[kWaves][kTileW];  // per-run minimum of the labelling pass
-    __shared__ uint32_t ntie;
+    uint32_t* const P = sh.P;
+    uint64_t* const raw_r = sh.raw_r;
+    uint64_t* const raw_d = sh.raw_d;
+    uint8_t* const halo = sh.halo;
+    uint32_t& ntie = sh.ntie;
+    extern __shared__ uint32_t cut[];  // clock: the q x q cutoff slice (sized at launch)
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const uint32_t ulane = threadIdx.x & 63u;
+    // the wave index is uniform: keeping it (and every row index derived from
+    // it) in scalar registers lets row accesses take a scalar row pointer and
+    // the lane as a 32-bit offset
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int L = a.L, q = a.q;
     const int x0 = tx * kTileW, y0 = ty * kTileH;
     const int x = x0 + lane;
@@ -256,9 +270,9 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // 24-bit multiplies (L < 2^16) replaces 64-bit address products.
     const uint32_t tile_base = __umul24(y0, L) + static_cast<uint32_t>(x0);
     const size_t tile = static_cast<size_t>(ty) * a.tiles_x + tx;
-    const bool col_ok = x < L;
-    const int nvalid = min(kTileW, L - x0);
-    const int nrows = min(kTileH, L - y0);
+    const bool col_ok = kFull || x < L;
+    const int nvalid = kFull ? kTileW : min(kTileW, L - x0);
+    const int nrows = kFull ? kTileH : min(kTileH, L - y0);
     // lanes whose right bond stays inside the tile (not the last column, no wrap)
     const uint64_t in_tile_r = (nvalid >= 64) ? (~0ull >> 1) : ((1ull << (nvalid - 1)) - 1ull);
     const uint64_t t = a.ctl->t;
@@ -285,49 +299,50 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // the column right of the tile: one site per lane of wave 0
     const int xh = (x0 + nvalid == L) ? 0 : x0 + nvalid;
     const int yh = y0 + lane;
-    const bool halo_lane = wave == 0 && yh < L;
-    const uint32_t ih = __umul24(min(yh, L - 1), L) + static_cast<uint32_t>(xh);
+    const bool halo_lane = wave == 0 && (kFull || yh < L);
+    const uint32_t ih = __umul24(kFull ? yh : min(yh, L - 1), L) + static_cast<uint32_t>(xh);
     if (!kFused && wave == 0) halo[lane] = halo_lane ? static_cast<uint8_t>(a.spins[ih]) : 0;
 
     const int ly_base = wave * RPW;
     const int y_base = y0 + ly_base;
     int sreg[RPW + 1];
+    // row r of the strip (r == RPW: the row below it); row L is row 0, the
+    // periodic neighbour of row L - 1 (in a full tile only the row below a
+    // strip can be row L)
+    auto row_of = [&](int r) -> int {
+        const int yr = y_base + r;
+        return ((!kFull || r == RPW) && yr == L) ? 0 : yr;
+    };
+    auto row_ok = [&](int r) -> bool { return kFull || (col_ok && y_base + r <= L); };
     if (kFused) {
         // the paths of the RPW + 1 sites of this lane (and of its halo site
         // in wave 0) are followed together
         uint32_t w[RPW + 2];
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
-            const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
-            w[r] = (col_ok && yr <= L) ? a.labels_prev[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : kRootFlag;
+            const uint32_t* row = a.labels_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0));
+            w[r] = row_ok(r) ? row[ulane] : kRootFlag;
         }
         w[RPW + 1] = halo_lane ? a.labels_prev[ih] : kRootFlag;
-        bool pending = true;
-        while (pending) {
-            pending = false;
+        // the previous forest holds root words at its roots and copies of them
+        // at its linked tile-local roots, and every other site names its
+        // tile-local root: one more load reaches a root word
 #pragma unroll
-            for (int r = 0; r <= RPW + 1; ++r)
-                if (!(w[r] & kRootFlag)) {
-                    w[r] = a.labels_prev[w[r]];
-                    pending = true;
-                }
-        }
+        for (int r = 0; r <= RPW + 1; ++r)
+            if (!(w[r] & kRootFlag)) w[r] = a.labels_prev[w[r]];
         if (wave == 0)
             halo[lane] = halo_lane ? static_cast<uint8_t>(flipped<kClock>(w[RPW + 1], kClock ? a.spins_prev[ih] : 0, m_prev, q)) : 0;
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
-            const int yr = y_base + r;
-            const bool ok = col_ok && yr <= L;
-            const uint32_t i = __umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x);
-            sreg[r] = ok ? flipped<kClock>(w[r], kClock ? a.spins_prev[i] : 0, m_prev, q) : 0;
+            const uint32_t rb = __umul24(row_of(r), L) + static_cast<uint32_t>(x0);
+            sreg[r] = row_ok(r) ? flipped<kClock>(w[r], kClock ? (a.spins_prev + rb)[ulane] : 0, m_prev, q) : 0;
             // the new state of this wave's own rows
-            if (r < RPW && col_ok && yr < L) a.spins[i] = static_cast<int8_t>(sreg[r]);
+            if (r < RPW && (kFull || (col_ok && y_base + r < L))) (a.spins + rb)[ulane] = static_cast<int8_t>(sreg[r]);
         }
     } else {
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
-            const int yr = y_base + r;  // yr == L is row 0 (the periodic neighbour of row L-1)
-            sreg[r] = (col_ok && yr <= L) ? a.spins[__umul24(yr == L ? 0 : yr, L) + static_cast<uint32_t>(x)] : 0;
+            sreg[r] = row_ok(r) ? (a.spins + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0)))[ulane] : 0;
         }
     }
     __syncthreads();  // halo and cutoffs in LDS
@@ -344,12 +359,12 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const int ly0 = ly_base + g * 8;
         const int yb = y0 + ly0;  // multiple of 8
         Words4 hi = {0, 0, 0, 0};
-        if (col_ok && yb < L) hi = draw(__umul24(yb >> 3, L) + static_cast<uint32_t>(x), t, kBondHi, k0, k1);
+        if (kFull || (col_ok && yb < L)) hi = draw(__umul24(yb >> 3, L) + static_cast<uint32_t>(x), t, kBondHi, k0, k1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int r = g * 8 + k;
             const int ly = ly0 + k;
-            const bool ok = col_ok && (yb + k < L);
+            const bool ok = kFull || (col_ok && (yb + k < L));
             const int s = sreg[r];
             const int sd = sreg[r + 1];
             const int sr_next = __builtin_amdgcn_mov_dpp(s, 0x130, 0xF, 0xF, false);  // wave_shl:1, lane i <- i+1
@@ -369,7 +384,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 td = ok && (hd == (cd >> 24)) && (cd & 0xFFFFFFu);
             } else {
                 // Potts: a bond needs equal spins and a high byte below the cutoff's
-                const uint64_t okm = __ballot(ok);
+                const uint64_t okm = kFull ? ~0ull : __ballot(ok);
                 const uint64_t er = __ballot(s == sr), ed = __ballot(s == sd);
                 mr = okm & er & __ballot(hr < chi);
                 md = okm & ed & __ballot(hd < chi);
@@ -421,7 +436,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     if (threadIdx.x < 2 * kTileH) {
         const int ly = threadIdx.x & (kTileH - 1);
         const int y = y0 + ly;
-        if (y < L) {
+        if (kFull || y < L) {
             const uint32_t wi = __umul24(y, a.w64) + static_cast<uint32_t>(tx);
             if (threadIdx.x < kTileH)
                 a.bond_r[wi] = raw_r[ly];
@@ -431,7 +446,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
     // Border record, bond masks (lane = row of the tile for the column masks).
     if (wave == kWaves - 1) {
-        const bool rowok = lane < nrows;
+        const bool rowok = kFull || lane < nrows;
         const uint64_t rr = raw_r[lane], dd = raw_d[lane];
         const uint64_t right_r = __ballot(rowok && ((rr >> (nvalid - 1)) & 1ull));
         const uint64_t right_d = __ballot(rowok && ((dd >> (nvalid - 1)) & 1ull));
@@ -452,30 +467,39 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // joined to that one.  P holds, for each site, its run's first site, and
     // for a run's first site, the run's label.
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    uint32_t run_start_rows = 0;
+    // A bond mask read from LDS is uniform: two lane reads put it in scalar
+    // registers, where the test of a lane's bit costs no vector instruction.
+    auto uniform64 = [](uint64_t v) -> uint64_t {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+        return (static_cast<uint64_t>(hi) << 32) | lo;
+    };
+    const uint64_t le_lane = ~0ull >> (63 - lane);  // this lane and the lanes below it
     {
-        uint32_t* my_slot = slot[wave];
+        uint32_t* my_slot = sh.slot[wave];
         uint32_t lab_prev = kNone;
+        uint64_t d_above = 0;  // down bonds of the row above (within the strip)
+#pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int ly = ly_base + r;
-            const uint64_t ir = raw_r[ly] & in_tile_r;
-            const int start = 63 - __clzll(~(ir << 1) & (~0ull >> (63 - lane)));
-            if (start == lane) run_start_rows |= 1u << r;
+            const uint64_t starts = ~((uniform64(raw_r[ly]) & in_tile_r) << 1);  // first sites of the runs
+            const int start = 63 - __clzll(starts & le_lane);
+            const bool run_start = __builtin_amdgcn_inverse_ballot_w64(starts);
             const uint32_t node = static_cast<uint32_t>(ly * kTileW + start);
             // the label above is usually still a root: one load, and the
             // find loop runs only where it is not
             uint32_t cand = kNone;
-            if (r > 0 && y0 + ly < L && ((raw_d[ly - 1] >> lane) & 1ull)) {
+            if (r > 0 && (kFull || y0 + ly < L) && __builtin_amdgcn_inverse_ballot_w64(d_above)) {
                 const uint32_t p = lds_load(&P[lab_prev]);
                 cand = (p == lab_prev) ? p : lds_find_from(P, lab_prev, p);
             }
-            if (start == lane) my_slot[lane] = kNone;
+            if (run_start) my_slot[lane] = kNone;
             __builtin_amdgcn_wave_barrier();
             if (cand != kNone) atomicMin(&my_slot[start], cand);
             __builtin_amdgcn_wave_barrier();
             const uint32_t m = my_slot[start];
             const uint32_t lab = (m == kNone) ? node : m;
-            P[ly * kTileW + lane] = (start == lane) ? lab : node;
+            P[ly * kTileW + lane] = run_start ? lab : node;
             __builtin_amdgcn_wave_barrier();
             // cand and m were roots when found (m < cand); link cand under m
             // at once, and join its new parent too if it was linked meanwhile
@@ -484,6 +508,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 if (old != cand) lds_union(P, old, m);
             }
             lab_prev = lab;
+            d_above = uniform64(raw_d[ly]);
         }
     }
     __syncthreads();
@@ -493,7 +518,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // between the same two runs.
     if (wave + 1 < kWaves) {
         const int ly = ly_base + RPW - 1;
-        const uint64_t d = (y0 + ly + 1 < L) ? raw_d[ly] : 0ull;
+        const uint64_t d = (kFull || y0 + ly + 1 < L) ? raw_d[ly] : 0ull;
         if (((d >> lane) & 1ull) &&
             !(lane > 0 && ((d >> (lane - 1)) & 1ull) && ((raw_r[ly] >> (lane - 1)) & 1ull) &&
               ((raw_r[ly + 1] >> (lane - 1)) & 1ull)))
@@ -505,7 +530,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // root, after which any site reaches its root in two loads.
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-        if ((run_start_rows >> r) & 1u) {
+        if (__builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1))) {
             // usually the run's label is itself a root: two loads, no store
             const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
             const uint32_t p = lds_load(&P[self]);
@@ -527,12 +552,12 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     static_assert(kWaves == 4 && kTileW == 64 && kTileH == 64, "one wave per tile edge, one lane per position");
     {
         int ly = lane, lx = lane;
-        bool valid = lane < nrows;
+        bool valid = kFull || lane < nrows;
         if (wave == 0) lx = nvalid - 1;
         if (wave == 2) lx = 0;
         if (wave == 1 || wave == 3) {
             ly = (wave == 1) ? nrows - 1 : 0;
-            valid = lane < nvalid;
+            valid = kFull || lane < nvalid;
         }
         if (valid) {
             const uint32_t root = P[P[ly * kTileW + lx]];
@@ -546,16 +571,19 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const int y = y_base + r;
-        const bool ok = col_ok && (y < L);
+        const bool ok = kFull || (col_ok && (y < L));
         const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
         const uint32_t root = rootreg[r];
-        const bool is_root = ok && (root == self);
+        const uint64_t rm = __ballot(ok && root == self);  // the row's roots
+        const bool is_root = __builtin_amdgcn_inverse_ballot_w64(rm);
         // every site of the row is stored (a root gets a placeholder root word
         // that its draw below overwrites), so label lines are written whole
         const uint32_t i = __umul24(y, L) + static_cast<uint32_t>(x);
-        if (ok) a.labels[i] = is_root ? kRootFlag : tile_base + __umul24(root >> 6, L) + (root & 63u);
-        const uint64_t rm = __ballot(is_root);
-        if (is_root) list[nroots + static_cast<uint32_t>(__popcll(rm & ((1ull << lane) - 1ull)))] = i;
+        if (ok) (a.labels + (__umul24(y, L) + static_cast<uint32_t>(x0)))[ulane] =
+            is_root ? kRootFlag : tile_base + __umul24(root >> 6, L) + (root & 63u);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(rm >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(rm), 0u));
+        if (is_root) list[nroots + below] = i;
         nroots += static_cast<uint32_t>(__popcll(rm));
     }
     __syncthreads();
@@ -567,6 +595,15 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t v = kClock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
         a.labels[i] = kRootFlag | v;
     }
+}
+
+template <int kModel, bool kFused>
+__device__ __forceinline__ void bond_tile(const SweepArgs& a, const int tx, const int ty) {
+    __shared__ BondShared sh;
+    if ((tx + 1) * kTileW <= a.L && (ty + 1) * kTileH <= a.L)
+        bond_local_tile<kModel, kFused, true>(a, tx, ty, sh);
+    else
+        bond_local_tile<kModel, kFused, false>(a, tx, ty, sh);
 }
 
 // Thread g of a launch over the bonds that cross every step-th tile border
@@ -763,6 +800,20 @@ __device__ __forceinline__ void flatten_root(uint32_t* lab, uint32_t r) {
     lab[r] = x;
 }
 
+// The same for a forest that only the flip reads: the linked tile-local root
+// receives a copy of its cluster's root word, so that any site reaches a root
+// word in at most two loads (site -> tile-local root).  Nothing else is
+// written: a halving store could overwrite a copy another thread had just
+// stored.  Every linked node is the end of some border bond, so every one of
+// them is visited.
+__device__ __forceinline__ void copy_root_word(uint32_t* lab, uint32_t r) {
+    uint32_t w = lab[r];
+    if (w & kRootFlag) return;  // a cluster root, or a copy already
+    do w = lab[w];
+    while (!(w & kRootFlag));
+    lab[r] = w;
+}
+
 __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block) {
     if (!a.ctl->live) return;
     // Every kernel that reads the sweep index has finished (stream order); the
@@ -775,8 +826,14 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
     const uint32_t i = b.active ? b.i : kRootFlag, j = b.active ? b.j : kRootFlag;
     const uint32_t pi = __shfl_up(i, 1, 64), pj = __shfl_up(j, 1, 64);
     const bool first = (threadIdx.x & 63) == 0;
-    if (b.active && (first || pi != i)) flatten_root(a.labels, i);
-    if (b.active && (first || pj != j)) flatten_root(a.labels, j);
+    const bool do_i = b.active && (first || pi != i), do_j = b.active && (first || pj != j);
+    if (a.root_copies) {
+        if (do_i) copy_root_word(a.labels, i);
+        if (do_j) copy_root_word(a.labels, j);
+    } else {
+        if (do_i) flatten_root(a.labels, i);
+        if (do_j) flatten_root(a.labels, j);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,19 +1141,19 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
 template <int kModel>
 __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_local_tile<kModel, false>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<kModel, false>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 // Eight waves per SIMD (the scalar registers over the limit spill to vector
 // lanes).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_local_tile<0, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<0, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_clock(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_local_tile<1, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<1, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
@@ -1133,7 +1190,7 @@ template <int kModel>
 __global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    bond_local_tile<kModel, false>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+    bond_tile<kModel, false>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {

@@ -449,6 +449,9 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         }
         st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(a, c->stream); });
         if (st) return st;
+        // a verified sweep's canonical labels need the links; otherwise the
+        // flatten leaves root words where the next flip looks
+        a.root_copies = verify ? 0 : 1;
         st = timed(c, profile, kKFlatten, [&] { return launch_flatten(a, c->stream); });
         if (st) return st;
         if (last) {
