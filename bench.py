@@ -229,7 +229,7 @@ def main() -> int:
     lat = swmc.Lattice(cfg.L, cfg.q, cfg.model, T=cfg.T, J=cfg.J, seed=cfg.seed)
     lat.sweep(args.warmup)
     # the autotuner picks the merge schedule on the warmed-up state and restores it
-    schedule = lat.tune(5)
+    schedule = lat.tune(10)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
