@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
             "or_flip_at": (None, [c_int, c_int, c_u64, c_u64, c_i64, i32p, i8p, i8p]),
             "or_sweep": (c_i64, [c_int, c_int, c_int, u32p, c_u64, c_u64, i8p, u8p, u8p, i32p]),
             "or_counts": (None, [c_int, c_int, i8p, i64p, i64p]),
+            "or_corr_counts": (None, [c_int, c_int, i8p, c_int, i64p]),
+            "or_corr_g": (c_dbl, [c_int, c_int, i64p]),
             "or_observables": (None, [c_int, c_int, c_int, c_dbl, i64p, i64p, f64p, f64p]),
             "or_run": (c_int, [c_int, c_int, c_int, c_dbl, c_dbl, c_u64, c_i64, c_i64, i8p, f64p, f64p]),
             "or_transition_counts": (c_int, [c_int, c_int, c_int, c_dbl, c_dbl, i8p, c_u64, c_u64, c_i64, i64p]),
@@ -205,6 +207,10 @@ class Chain:
             self.t += 1
         return self
 
+    def corr_counts(self):
+        """Correlation counts of the current state at r = L/4 and r = L/2 (Sec. 4)."""
+        return corr_counts(self.L, self.q, self.spins, self.L // 4), corr_counts(self.L, self.q, self.spins, self.L // 2)
+
     def counts(self):
         h = np.zeros(32, dtype=np.int64)
         p = np.zeros(32, dtype=np.int64)
@@ -223,6 +229,21 @@ class Chain:
         lib().or_observables(self.L, self.q, self.model, self.J, _p(h32, ctypes.c_int64),
                              _p(p32, ctypes.c_int64), ctypes.byref(e), ctypes.byref(m2))
         return e.value, m2.value
+
+
+def corr_counts(L, q, spins, r) -> np.ndarray:
+    """Histogram of (s_{i+r} - s_i) mod q over both directions (2N pairs), Sec. 4."""
+    s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
+    h = np.zeros(32, dtype=np.int64)
+    lib().or_corr_counts(L, q, _p(s, ctypes.c_int8), int(r), _p(h, ctypes.c_int64))
+    return h[:q].copy()
+
+
+def corr_g(L, q, corr_hist) -> float:
+    """G(r) = <S_i . S_{i+r}> from the correlation counts (Sec. 4)."""
+    h = np.zeros(32, dtype=np.int64)
+    h[: len(corr_hist)] = corr_hist
+    return float(lib().or_corr_g(L, q, _p(h, ctypes.c_int64)))
 
 
 def observables_from_counts(L, q, model, J, hist, pair_hist):

@@ -363,6 +363,32 @@ void or_counts(int L, int q, const int8_t* spins, int64_t* hist, int64_t* pair_h
     }
 }
 
+/* Correlation counts at distance r (Sec. 4, the clock model's correlation
+ * function): over every site i and both lattice directions, the histogram of
+ * (s_j - s_i) mod q for the site j = i + r in that direction (periodic).
+ * 2N pairs in all. */
+void or_corr_counts(int L, int q, const int8_t* spins, int r, int64_t* corr_hist) {
+    for (int k = 0; k < q; ++k) corr_hist[k] = 0;
+    for (int y = 0; y < L; ++y) {
+        for (int x = 0; x < L; ++x) {
+            int s = spins[(int64_t)y * L + x];
+            int sx = spins[(int64_t)y * L + (x + r) % L];
+            int sy = spins[(int64_t)((y + r) % L) * L + x];
+            corr_hist[((sx - s) % q + q) % q] += 1;
+            corr_hist[((sy - s) % q + q) % q] += 1;
+        }
+    }
+}
+
+/* G(r) = <S_i^x S_{i+r}^x + S_i^y S_{i+r}^y>: the mean over the 2N pairs of
+ * cos(theta_j - theta_i), theta = 2 pi s / q, from the counts above. */
+double or_corr_g(int L, int q, const int64_t* corr_hist) {
+    double N = (double)L * (double)L;
+    double g = 0.0;
+    for (int d = 0; d < q; ++d) g += (double)corr_hist[d] * cos_turn(d, q);
+    return g / (2.0 * N);
+}
+
 void or_observables(int L, int q, int model, double J, const int64_t* hist,
                     const int64_t* pair_hist, double* e_per_site, double* m2) {
     double N = (double)L * (double)L;

@@ -78,6 +78,11 @@ int64_t or_sweep(int L, int q, int model, const uint32_t* table, uint64_t seed, 
 /* Integer counts of a state: hist[k] (k<q) and pair_hist[d] over the 2N owned
  * bonds, d = (s_j - s_i) mod q. */
 void or_counts(int L, int q, const int8_t* spins, int64_t* hist, int64_t* pair_hist);
+/* Correlation counts at distance r: the histogram of (s_j - s_i) mod q over
+ * the 2N pairs j = i + r (x direction) and j = i + r (y direction), periodic;
+ * and G(r) from them (mean of cos(theta_j - theta_i)). */
+void or_corr_counts(int L, int q, const int8_t* spins, int r, int64_t* corr_hist);
+double or_corr_g(int L, int q, const int64_t* corr_hist);
 /* Observables from counts: energy per site and M^2 / N^2 (Potts order
  * parameter of the paper, or |M|^2/N^2 for the clock model). */
 void or_observables(int L, int q, int model, double J, const int64_t* hist,
