@@ -84,6 +84,17 @@ typedef struct {
     int64_t pair_hist[32];/* owned bonds (2N) by (s_j - s_i) mod q */
     double e_per_site, m2;
     double mean_e, mean_m2, mean_m4, binder_u;
+    /* Clock model only (zero for Potts): the correlation function of Sec. 4,
+     * G(r) = <S_i^x S_{i+r}^x + S_i^y S_{i+r}^y>, at r = L/4 and r = L/2 (integer
+     * division).  corr_hist[0] and corr_hist[1] count the 2N pairs (i, i + r x)
+     * and (i, i + r y) (periodic) by (s_j - s_i) mod q, for r = L/4 and L/2;
+     * g_quarter and g_half are G of the current state (FP64 from the counts);
+     * mean_g_* are running averages over the measured sweeps and
+     * corr_ratio = mean_g_half / mean_g_quarter is the ratio R(T) (0 while
+     * mean_g_quarter is 0). */
+    int64_t corr_hist[2][32];
+    double g_quarter, g_half;
+    double mean_g_quarter, mean_g_half, corr_ratio;
 } sw_obs;
 
 typedef struct sw_ctx sw_ctx;

@@ -89,13 +89,7 @@ class Lattice:
     def measure(self) -> dict:
         o = SwObs()
         check(_lib.lib().sw_measure(self._ctx, ctypes.byref(o)), "sw_measure")
-        return {
-            "t": int(o.sweeps_done), "samples": int(o.samples),
-            "hist": np.array(o.hist[: self.q], dtype=np.int64),
-            "pair_hist": np.array(o.pair_hist[: self.q], dtype=np.int64),
-            "e": o.e_per_site, "m2": o.m2, "mean_e": o.mean_e, "mean_m2": o.mean_m2,
-            "mean_m4": o.mean_m4, "binder_u": o.binder_u,
-        }
+        return _obs_dict(o, self.q)
 
     # -- state ---------------------------------------------------------------
     def spins(self) -> np.ndarray:
@@ -168,6 +162,10 @@ def _obs_dict(o: SwObs, q: int) -> dict:
         "hist": np.array(o.hist[:q], dtype=np.int64), "pair_hist": np.array(o.pair_hist[:q], dtype=np.int64),
         "e": o.e_per_site, "m2": o.m2, "mean_e": o.mean_e, "mean_m2": o.mean_m2,
         "mean_m4": o.mean_m4, "binder_u": o.binder_u,
+        # clock model (Sec. 4): correlation counts and G at r = L/4 and L/2, R = <G(L/2)>/<G(L/4)>
+        "corr_hist": np.array([o.corr_hist[0][:q], o.corr_hist[1][:q]], dtype=np.int64),
+        "g_quarter": o.g_quarter, "g_half": o.g_half, "mean_g_quarter": o.mean_g_quarter,
+        "mean_g_half": o.mean_g_half, "corr_ratio": o.corr_ratio,
     }
 
 

@@ -36,6 +36,12 @@ class SwObs(ctypes.Structure):
         ("mean_m2", ctypes.c_double),
         ("mean_m4", ctypes.c_double),
         ("binder_u", ctypes.c_double),
+        ("corr_hist", (ctypes.c_int64 * 32) * 2),
+        ("g_quarter", ctypes.c_double),
+        ("g_half", ctypes.c_double),
+        ("mean_g_quarter", ctypes.c_double),
+        ("mean_g_half", ctypes.c_double),
+        ("corr_ratio", ctypes.c_double),
     ]
 
 

@@ -32,8 +32,7 @@ struct Replica {
     size_t offset = 0;
     SweepArgs args{};
     std::vector<uint32_t> table;
-    uint64_t samples = 0;
-    double sum_e = 0.0, sum_m2 = 0.0, sum_m4 = 0.0;
+    Sums sums;  // running sums over measured sweeps
     bool have_canon = false;
 };
 
@@ -246,11 +245,7 @@ int flush_rings(sw_batch* b, int rows) {
         SWB_HIP(b, hipMemcpy(b->ring_host.data(), b->base + rp.offset + rp.lay.ring, b->ring_host.size() * 8,
                              hipMemcpyDeviceToHost));
         for (int r = 0; r < rows; ++r) {
-            const Observables o = observables_of(rp.p, b->ring_host.data() + static_cast<size_t>(r) * kRowWords);
-            rp.sum_e += o.e;
-            rp.sum_m2 += o.m2;
-            rp.sum_m4 += o.m2 * o.m2;
-            rp.samples += 1;
+            rp.sums.add(observables_of(rp.p, b->ring_host.data() + static_cast<size_t>(r) * kRowWords));
         }
     }
     return SW_OK;
@@ -416,7 +411,7 @@ int sw_batch_measure(sw_batch* b, int32_t replica, sw_obs* out) {
     SWB_HIP(b, hipStreamSynchronize(b->stream));
     SWB_HIP(b, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
     SWB_HIP(b, hipMemcpy(&ctl, b->base + rp.offset + rp.lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
-    fill_obs(rp.p, row, ctl.t, rp.samples, rp.sum_e, rp.sum_m2, rp.sum_m4, out);
+    fill_obs(rp.p, row, ctl.t, rp.sums, out);
     return SW_OK;
 }
 

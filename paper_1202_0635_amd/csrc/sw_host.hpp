@@ -34,10 +34,23 @@ Layout layout_of(const sw_lattice& p, bool with_pair = false);
 
 struct Observables {
     double e = 0.0, m2 = 0.0;
+    double g1 = 0.0, g2 = 0.0;  // clock: G(L/4), G(L/2)
 };
 Observables observables_of(const sw_lattice& p, const int64_t* row);
-void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, uint64_t samples, double sum_e, double sum_m2,
-              double sum_m4, sw_obs* out);
+// Running sums over the measured sweeps, folded in sweep order.
+struct Sums {
+    uint64_t samples = 0;
+    double e = 0.0, m2 = 0.0, m4 = 0.0, g1 = 0.0, g2 = 0.0;
+    void add(const Observables& o) {
+        samples += 1;
+        e += o.e;
+        m2 += o.m2;
+        m4 += o.m2 * o.m2;
+        g1 += o.g1;
+        g2 += o.g2;
+    }
+};
+void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, const Sums& sums, sw_obs* out);
 
 SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay);
 // Control block of a fresh lattice: t = 0, no sweep target.

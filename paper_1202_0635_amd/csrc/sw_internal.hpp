@@ -48,7 +48,10 @@ enum BorderMask {
     kTopR = 5,     // right bonds of the top row
     kBorderMasks = 8
 };
-constexpr int kRowWords = 64;    // int64 per count row: hist[32], pair_hist[32]
+// int64 per count row: hist[32], pair_hist[32], and for the clock model the
+// correlation histograms at r = L/4 and L/2 (Sec. 4)
+constexpr int kRowWords = 128;
+constexpr int kRowHist = 0, kRowPair = 32, kRowCorr1 = 64, kRowCorr2 = 96;
 
 // Device control block at the start of the arena.
 struct Control {

@@ -952,15 +952,17 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
 }
 
 // ---------------------------------------------------------------------------
-// Integer counts of the current state: n[k] and the owned-bond histogram of
-// (s_j - s_i) mod q.  Workgroup b takes rows b, b + nblocks, ...; thread t
-// takes groups of four consecutive sites, packed one byte per site in a
-// 32-bit word (the row, the row below, and the right neighbours), and four
-// groups of a row are loaded before any is counted.  q = 2 counts by
-// popcounts of the packed words; q <= 8 by wave ballots with the bins
-// unrolled (scalar registers); larger q by LDS atomics.  Each workgroup
-// stores its bins to its own partial row (thousands of global atomics on the
-// same few words would serialise) and one workgroup sums the partial rows.
+// Integer counts of the current state: n[k], the owned-bond histogram of
+// (s_j - s_i) mod q, and for the clock model the correlation histograms of
+// (s_{i+r} - s_i) mod q over both lattice directions at r = L/4 and L/2
+// (Sec. 4).  Workgroup b takes rows b, b + nblocks, ...; thread t takes
+// groups of four consecutive sites, packed one byte per site in a 32-bit word
+// (the row, the row below, the right neighbours and the displaced sites), and
+// four groups of a row are loaded before any is counted.  Potts q = 2 counts
+// by popcounts of the packed words; q <= 8 in per-lane LDS bins; larger q by
+// shared LDS atomics.  Each workgroup stores its bins to its own partial row
+// (thousands of global atomics on the same few words would serialise) and
+// one workgroup sums the partial rows.
 // ---------------------------------------------------------------------------
 constexpr int kCountThreads = 256;
 constexpr int kGroupSpan = 4 * kCountThreads;  // sites of a row per step of the workgroup
@@ -968,12 +970,26 @@ constexpr int kGroups = 4;                     // steps of a row whose loads are
 
 struct Group4 {
     uint32_t w, wr, v;  // spins of four sites, of their right and lower neighbours
+    uint32_t cx1, cy1, cx2, cy2;  // sites r = L/4 and L/2 to the right and below (clock model)
     int n;              // sites of the group inside the row (0..4)
 };
 
-__device__ __forceinline__ Group4 load_group(const int8_t* spins, uint32_t here, uint32_t below, int x, int L,
-                                             bool aligned, int first) {
-    Group4 g{0u, 0u, 0u, max(0, min(4, L - x))};
+// Four consecutive sites of the row at byte offset row, from column x on
+// (columns wrap at L); n of them are wanted.
+__device__ __forceinline__ uint32_t load4(const int8_t* spins, uint32_t row, int x, int L, int n, bool aligned) {
+    if (aligned && n == 4 && (x & 3) == 0 && x + 3 < L) return *reinterpret_cast<const uint32_t*>(spins + row + x);
+    uint32_t w = 0;
+    for (int j = 0; j < n; ++j) {
+        const int xj = (x + j < L) ? x + j : x + j - L;
+        w |= static_cast<uint32_t>(static_cast<uint8_t>(spins[row + xj])) << (8 * j);
+    }
+    return w;
+}
+
+template <bool kCorr>
+__device__ __forceinline__ Group4 load_group(const int8_t* spins, uint32_t here, uint32_t below, uint32_t far1,
+                                             uint32_t far2, int x, int L, bool aligned, int first) {
+    Group4 g{0u, 0u, 0u, 0u, 0u, 0u, 0u, max(0, min(4, L - x))};
     if (aligned && g.n == 4) {
         g.w = *reinterpret_cast<const uint32_t*>(spins + here + x);
         g.v = *reinterpret_cast<const uint32_t*>(spins + below + x);
@@ -987,24 +1003,35 @@ __device__ __forceinline__ Group4 load_group(const int8_t* spins, uint32_t here,
             g.wr |= r << (8 * j);
         }
     }
+    if (kCorr && g.n > 0) {
+        const int r1 = L / 4, r2 = L / 2;
+        const int x1 = (x + r1 < L) ? x + r1 : x + r1 - L, x2 = (x + r2 < L) ? x + r2 : x + r2 - L;
+        g.cx1 = load4(spins, here, x1, L, g.n, aligned);
+        g.cx2 = load4(spins, here, x2, L, g.n, aligned);
+        g.cy1 = load4(spins, far1, x, L, g.n, aligned);
+        g.cy2 = load4(spins, far2, x, L, g.n, aligned);
+    }
     return g;
 }
 
 // Calls f(group) for every group of four sites of this workgroup's rows.
-template <typename F>
+template <bool kCorr, typename F>
 __device__ __forceinline__ void for_groups(const SweepArgs& a, uint32_t block, uint32_t nblocks, F&& f) {
     const int L = a.L;
     const bool aligned = (L & 3) == 0;
+    const int r1 = L / 4, r2 = L / 2;
     for (int y = static_cast<int>(block); y < L; y += static_cast<int>(nblocks)) {
         const uint32_t here = __umul24(y, L);
         const uint32_t below = __umul24((y + 1 == L) ? 0 : y + 1, L);
+        const uint32_t far1 = kCorr ? __umul24((y + r1 < L) ? y + r1 : y + r1 - L, L) : 0u;
+        const uint32_t far2 = kCorr ? __umul24((y + r2 < L) ? y + r2 : y + r2 - L, L) : 0u;
         const int first = static_cast<uint8_t>(a.spins[here]);  // right neighbour of the row's last site
         for (int xb = 0; xb < L; xb += kGroups * kGroupSpan) {
             Group4 g[kGroups];
 #pragma unroll
             for (int u = 0; u < kGroups; ++u)
-                g[u] = load_group(a.spins, here, below, xb + u * kGroupSpan + 4 * static_cast<int>(threadIdx.x), L,
-                                  aligned, first);
+                g[u] = load_group<kCorr>(a.spins, here, below, far1, far2,
+                                         xb + u * kGroupSpan + 4 * static_cast<int>(threadIdx.x), L, aligned, first);
 #pragma unroll
             for (int u = 0; u < kGroups; ++u) f(g[u]);
         }
@@ -1017,11 +1044,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// q = 2: bytes are 0 or 1, so a popcount of a packed word (or of the xor of
-// two) counts ones (or unequal pairs) among its valid bytes.
+// Potts q = 2: bytes are 0 or 1, so a popcount of a packed word (or of the
+// xor of two) counts ones (or unequal pairs) among its valid bytes.
 __device__ __forceinline__ void count_q2(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h) {
     uint32_t sites = 0, ones = 0, diff = 0;
-    for_groups(a, block, nblocks, [&](const Group4& g) {
+    for_groups<false>(a, block, nblocks, [&](const Group4& g) {
         const uint32_t m = (g.n >= 4) ? 0xFFFFFFFFu : ((1u << (8 * g.n)) - 1u);
         sites += static_cast<uint32_t>(g.n);
         ones += __popc(g.w & m);
@@ -1031,71 +1058,143 @@ __device__ __forceinline__ void count_q2(const SweepArgs& a, uint32_t block, uin
     ones = wave_sum(ones);
     diff = wave_sum(diff);
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&h[0], sites - ones);
-        atomicAdd(&h[1], ones);
-        atomicAdd(&h[32], 2u * sites - diff);
-        atomicAdd(&h[33], diff);
+        atomicAdd(&h[kRowHist + 0], sites - ones);
+        atomicAdd(&h[kRowHist + 1], ones);
+        atomicAdd(&h[kRowPair + 0], 2u * sites - diff);
+        atomicAdd(&h[kRowPair + 1], diff);
     }
 }
 
-template <int Q>
-__device__ __forceinline__ void count_ballot(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h) {
-    uint32_t cn[Q] = {}, cp[Q] = {};
-    for_groups(a, block, nblocks, [&](const Group4& g) {
+// q <= 8: every lane counts into bins of its own in LDS (bin b of lane l is
+// word b * 64 + l of its wave's block, so no two lanes ever add to one word
+// or one bank), and the workgroup folds them at the end.  Words 0-7: n[k]
+// (low half); 8-15: pairs by (s_j - s_i) mod q, right neighbour in the low
+// half, lower neighbour in the high half; 16-23 and 24-31: the correlation
+// pairs at L/4 and L/2, x displacement low, y displacement high.  A lane
+// adds at most 2^13 sites (L <= 46340 with 1024 workgroups of 256 threads),
+// so 16-bit halves cannot overflow.  Differences are taken four at a time by
+// byte-wise arithmetic on the packed words (no carries: every byte stays in
+// 0 .. 2q - 1).
+constexpr int kPrivHist = 0, kPrivPair = 8, kPrivCorr1 = 16, kPrivCorr2 = 24;
+__host__ __device__ constexpr int priv_bins(bool corr) { return corr ? 32 : 16; }
+constexpr int kCountWaves = kCountThreads / 64;
+
+// (t - s) mod q in every byte of packed words t, s (bytes < q <= 8)
+__device__ __forceinline__ uint32_t byte_diff_mod(uint32_t t, uint32_t s, uint32_t qq, uint32_t hi_q) {
+    const uint32_t d = t + qq - s;                          // t - s + q in 1 .. 2q - 1
+    const uint32_t ge = ((d + hi_q) >> 7) & 0x01010101u;    // 1 in the bytes where d >= q
+    return d - ge * (qq & 0xFFu);
+}
+
+template <bool kCorr>
+__device__ __forceinline__ void count_private(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h,
+                                              uint32_t* bins) {
+    constexpr int NB = priv_bins(kCorr);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < kCountWaves * NB * 64; k += kCountThreads) bins[k] = 0;
+    __syncthreads();
+    uint32_t* mine = bins + wave * NB * 64 + lane;
+    const uint32_t q = static_cast<uint32_t>(a.q);
+    const uint32_t qq = 0x01010101u * q, hi_q = 0x01010101u * (128u - q);
+    for_groups<kCorr>(a, block, nblocks, [&](const Group4& g) {
+        const uint32_t dr = byte_diff_mod(g.wr, g.w, qq, hi_q), dd = byte_diff_mod(g.v, g.w, qq, hi_q);
+        uint32_t d1 = 0, e1 = 0, d2 = 0, e2 = 0;
+        if (kCorr) {
+            d1 = byte_diff_mod(g.cx1, g.w, qq, hi_q);
+            e1 = byte_diff_mod(g.cy1, g.w, qq, hi_q);
+            d2 = byte_diff_mod(g.cx2, g.w, qq, hi_q);
+            e2 = byte_diff_mod(g.cy2, g.w, qq, hi_q);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const bool ok = j < g.n;
-            const int s = static_cast<int>((g.w >> (8 * j)) & 0xFFu);
-            int dr = static_cast<int>((g.wr >> (8 * j)) & 0xFFu) - s;
-            int dd = static_cast<int>((g.v >> (8 * j)) & 0xFFu) - s;
-            if (dr < 0) dr += Q;
-            if (dd < 0) dd += Q;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                cn[k] += static_cast<uint32_t>(__popcll(__ballot(ok && s == k)));
-                cp[k] += static_cast<uint32_t>(__popcll(__ballot(ok && dr == k)) + __popcll(__ballot(ok && dd == k)));
+            if (j >= g.n) break;
+            const int sh = 8 * j;
+            atomicAdd(&mine[64 * (kPrivHist + ((g.w >> sh) & 0xFFu))], 1u);
+            atomicAdd(&mine[64 * (kPrivPair + ((dr >> sh) & 0xFFu))], 1u);
+            atomicAdd(&mine[64 * (kPrivPair + ((dd >> sh) & 0xFFu))], 0x10000u);
+            if (kCorr) {
+                atomicAdd(&mine[64 * (kPrivCorr1 + ((d1 >> sh) & 0xFFu))], 1u);
+                atomicAdd(&mine[64 * (kPrivCorr1 + ((e1 >> sh) & 0xFFu))], 0x10000u);
+                atomicAdd(&mine[64 * (kPrivCorr2 + ((d2 >> sh) & 0xFFu))], 1u);
+                atomicAdd(&mine[64 * (kPrivCorr2 + ((e2 >> sh) & 0xFFu))], 0x10000u);
             }
         }
     });
-    if ((threadIdx.x & 63) == 0) {
+    __syncthreads();
+    // lane b of each wave adds word b over the wave's 64 lanes (both halves)
+    // into the first word of the bin; then thread o < 4q adds the waves
+    if (lane < static_cast<uint32_t>(NB)) {
+        const uint4* row = reinterpret_cast<const uint4*>(bins + (wave * NB + lane) * 64);
+        uint32_t sum = 0;
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            atomicAdd(&h[k], cn[k]);
-            atomicAdd(&h[32 + k], cp[k]);
+        for (int k = 0; k < 16; ++k) {
+            const uint4 v = row[k];
+            sum += (v.x & 0xFFFFu) + (v.x >> 16) + (v.y & 0xFFFFu) + (v.y >> 16) + (v.z & 0xFFFFu) + (v.z >> 16) +
+                   (v.w & 0xFFFFu) + (v.w >> 16);
         }
+        bins[(wave * NB + lane) * 64] = sum;
+    }
+    __syncthreads();
+    const int nout = kCorr ? 4 * static_cast<int>(q) : 2 * static_cast<int>(q);
+    const int o = static_cast<int>(threadIdx.x);
+    if (o < nout) {
+        const int kind = o / static_cast<int>(q), d = o % static_cast<int>(q);  // hist, pairs, corr L/4, corr L/2
+        uint32_t v = 0;
+#pragma unroll
+        for (int w = 0; w < kCountWaves; ++w) v += bins[(w * NB + 8 * kind + d) * 64];
+        h[32 * kind + d] = v;  // kRowHist, kRowPair, kRowCorr1, kRowCorr2
     }
 }
 
-__device__ __forceinline__ void count_lds(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h) {
+// q > 8: shared LDS bins and atomics.
+__device__ __forceinline__ void count_lds(const SweepArgs& a, uint32_t block, uint32_t nblocks, uint32_t* h, bool corr) {
     const int q = a.q;
-    for_groups(a, block, nblocks, [&](const Group4& g) {
+    auto delta = [q](uint32_t t, uint32_t s) -> int {
+        const int d = static_cast<int>(t) - static_cast<int>(s);
+        return d < 0 ? d + q : d;
+    };
+    auto body = [&](const Group4& g) {
         for (int j = 0; j < g.n; ++j) {
-            const int s = static_cast<int>((g.w >> (8 * j)) & 0xFFu);
-            int dr = static_cast<int>((g.wr >> (8 * j)) & 0xFFu) - s;
-            int dd = static_cast<int>((g.v >> (8 * j)) & 0xFFu) - s;
-            if (dr < 0) dr += q;
-            if (dd < 0) dd += q;
-            atomicAdd(&h[s], 1u);
-            atomicAdd(&h[32 + dr], 1u);
-            atomicAdd(&h[32 + dd], 1u);
+            const int sh = 8 * j;
+            const uint32_t s = (g.w >> sh) & 0xFFu;
+            atomicAdd(&h[kRowHist + s], 1u);
+            atomicAdd(&h[kRowPair + delta((g.wr >> sh) & 0xFFu, s)], 1u);
+            atomicAdd(&h[kRowPair + delta((g.v >> sh) & 0xFFu, s)], 1u);
+            if (corr) {
+                atomicAdd(&h[kRowCorr1 + delta((g.cx1 >> sh) & 0xFFu, s)], 1u);
+                atomicAdd(&h[kRowCorr1 + delta((g.cy1 >> sh) & 0xFFu, s)], 1u);
+                atomicAdd(&h[kRowCorr2 + delta((g.cx2 >> sh) & 0xFFu, s)], 1u);
+                atomicAdd(&h[kRowCorr2 + delta((g.cy2 >> sh) & 0xFFu, s)], 1u);
+            }
         }
-    });
+    };
+    if (corr)
+        for_groups<true>(a, block, nblocks, body);
+    else
+        for_groups<false>(a, block, nblocks, body);
+}
+
+// Dynamic LDS of the count kernel: the per-lane bins of the q <= 8 path.
+__host__ __device__ inline uint32_t count_lds_bytes(int q, int model) {
+    if (model == 0 && q == 2) return 0u;
+    if (q > 8) return 0u;
+    return static_cast<uint32_t>(kCountWaves * priv_bins(model == 1) * 64 * 4);
 }
 
 __device__ __forceinline__ void counts(const SweepArgs& a, const uint32_t block, const uint32_t nblocks) {
     __shared__ uint32_t h[kRowWords];
+    extern __shared__ uint32_t bins[];
     for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) h[k] = 0;
     __syncthreads();
-    switch (a.q) {
-        case 2: count_q2(a, block, nblocks, h); break;
-        case 3: count_ballot<3>(a, block, nblocks, h); break;
-        case 4: count_ballot<4>(a, block, nblocks, h); break;
-        case 5: count_ballot<5>(a, block, nblocks, h); break;
-        case 6: count_ballot<6>(a, block, nblocks, h); break;
-        case 7: count_ballot<7>(a, block, nblocks, h); break;
-        case 8: count_ballot<8>(a, block, nblocks, h); break;
-        default: count_lds(a, block, nblocks, h); break;
-    }
+    const bool clock = a.model == 1;
+    if (!clock && a.q == 2)
+        count_q2(a, block, nblocks, h);
+    else if (a.q > 8)
+        count_lds(a, block, nblocks, h, clock);
+    else if (clock)
+        count_private<true>(a, block, nblocks, h, bins);
+    else
+        count_private<false>(a, block, nblocks, h, bins);
     __syncthreads();
     uint32_t* part = a.count_partial + static_cast<size_t>(block) * kRowWords;
     for (int k = threadIdx.x; k < kRowWords; k += blockDim.x) part[k] = h[k];
@@ -1112,8 +1211,9 @@ __device__ __forceinline__ void count_sum(const SweepArgs& a, int64_t* row) {
     __syncthreads();
     const uint32_t nb = count_blocks(a.L);
     const int q = a.q;
-    for (int k = 0; k < 2 * q; ++k) {
-        const int bin = (k < q) ? k : 32 + (k - q);
+    const int kinds = (a.model == 1) ? 4 : 2;  // hist, pairs (, correlations at L/4 and L/2)
+    for (int k = 0; k < kinds * q; ++k) {
+        const int bin = (k / q) * 32 + k % q;
         unsigned long long v = 0;
         for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) v += a.count_partial[static_cast<size_t>(b) * kRowWords + bin];
 #pragma unroll
@@ -1292,7 +1392,7 @@ hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
 }
 
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_counts, dim3(count_blocks(a.L)), dim3(kCountThreads), 0, s, a);
+    hipLaunchKernelGGL(k_counts, dim3(count_blocks(a.L)), dim3(kCountThreads), count_lds_bytes(a.q, a.model), s, a);
     hipLaunchKernelGGL(k_count_sum, dim3(1), dim3(kCountSumThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -1313,7 +1413,7 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
         case kBKFlatten: hipLaunchKernelGGL(kb_flatten, grid, dim3(256), 0, s, m); break;
         case kBKFlip: hipLaunchKernelGGL(kb_flip<false>, grid, dim3(256), 0, s, m); break;
         case kBKFlipVerify: hipLaunchKernelGGL(kb_flip<true>, grid, dim3(256), 0, s, m); break;
-        case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(kCountThreads), 0, s, m); break;
+        case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(kCountThreads), count_lds_bytes(3, 1), s, m); break;
         case kBKCountSum: hipLaunchKernelGGL(kb_count_sum, grid, dim3(kCountSumThreads), 0, s, m, row); break;
         default: return hipErrorInvalidValue;
     }

@@ -135,8 +135,8 @@ Layout layout_of(const sw_lattice& p, bool with_pair) {
 Observables observables_of(const sw_lattice& p, const int64_t* row) {
     const double N = static_cast<double>(p.L) * static_cast<double>(p.L);
     const int q = p.q;
-    const int64_t* hist = row;
-    const int64_t* pair = row + 32;
+    const int64_t* hist = row + kRowHist;
+    const int64_t* pair = row + kRowPair;
     Observables o;
     if (p.model == SW_POTTS) {
         o.e = p.J * (2.0 * N - static_cast<double>(pair[0])) / N;
@@ -153,6 +153,14 @@ Observables observables_of(const sw_lattice& p, const int64_t* row) {
             my += static_cast<double>(hist[k]) * turn_sin(k, q);
         }
         o.m2 = (mx * mx + my * my) / (N * N);
+        // G(r): mean over the 2N displaced pairs of cos(theta_j - theta_i)
+        double g1 = 0.0, g2 = 0.0;
+        for (int d = 0; d < q; ++d) {
+            g1 += static_cast<double>(row[kRowCorr1 + d]) * turn_cos(d, q);
+            g2 += static_cast<double>(row[kRowCorr2 + d]) * turn_cos(d, q);
+        }
+        o.g1 = g1 / (2.0 * N);
+        o.g2 = g2 / (2.0 * N);
     }
     return o;
 }
@@ -203,24 +211,32 @@ SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     return a;
 }
 
-void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, uint64_t samples, double sum_e, double sum_m2,
-              double sum_m4, sw_obs* out) {
+void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, const Sums& sums, sw_obs* out) {
     std::memset(out, 0, sizeof *out);
     out->sweeps_done = t;
-    out->samples = samples;
+    out->samples = sums.samples;
     for (int k = 0; k < 32; ++k) {
-        out->hist[k] = row[k];
-        out->pair_hist[k] = row[32 + k];
+        out->hist[k] = row[kRowHist + k];
+        out->pair_hist[k] = row[kRowPair + k];
+        if (p.model == SW_CLOCK) {
+            out->corr_hist[0][k] = row[kRowCorr1 + k];
+            out->corr_hist[1][k] = row[kRowCorr2 + k];
+        }
     }
     const Observables o = observables_of(p, row);
     out->e_per_site = o.e;
     out->m2 = o.m2;
-    if (samples) {
-        const double n = static_cast<double>(samples);
-        out->mean_e = sum_e / n;
-        out->mean_m2 = sum_m2 / n;
-        out->mean_m4 = sum_m4 / n;
+    out->g_quarter = o.g1;
+    out->g_half = o.g2;
+    if (sums.samples) {
+        const double n = static_cast<double>(sums.samples);
+        out->mean_e = sums.e / n;
+        out->mean_m2 = sums.m2 / n;
+        out->mean_m4 = sums.m4 / n;
         out->binder_u = out->mean_m2 > 0.0 ? out->mean_m4 / (out->mean_m2 * out->mean_m2) : 0.0;
+        out->mean_g_quarter = sums.g1 / n;
+        out->mean_g_half = sums.g2 / n;
+        out->corr_ratio = out->mean_g_quarter != 0.0 ? out->mean_g_half / out->mean_g_quarter : 0.0;
     }
 }
 
@@ -237,9 +253,8 @@ struct sw_ctx {
     Layout lay{};
     SweepArgs args{};
     std::vector<uint32_t> table;
-    // running averages over measured sweeps
-    uint64_t samples = 0;
-    double sum_e = 0.0, sum_m2 = 0.0, sum_m4 = 0.0;
+    // running sums over measured sweeps
+    Sums sums;
     std::vector<int64_t> ring_host;
     // per-kernel timing
     std::vector<hipEvent_t> free_events;
@@ -303,11 +318,7 @@ int flush_ring(sw_ctx* c, int rows) {
     c->ring_host.resize(static_cast<size_t>(rows) * kRowWords);
     SW_HIP(c, hipMemcpy(c->ring_host.data(), c->base + c->lay.ring, c->ring_host.size() * 8, hipMemcpyDeviceToHost));
     for (int r = 0; r < rows; ++r) {
-        const Observables o = observables_of(c->p, c->ring_host.data() + static_cast<size_t>(r) * kRowWords);
-        c->sum_e += o.e;
-        c->sum_m2 += o.m2;
-        c->sum_m4 += o.m2 * o.m2;
-        c->samples += 1;
+        c->sums.add(observables_of(c->p, c->ring_host.data() + static_cast<size_t>(r) * kRowWords));
     }
     return SW_OK;
 }
@@ -482,7 +493,7 @@ int sw_measure(sw_ctx* c, sw_obs* out) {
     SW_HIP(c, hipStreamSynchronize(c->stream));
     SW_HIP(c, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
     SW_HIP(c, hipMemcpy(&ctl, c->base + c->lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
-    fill_obs(c->p, row, ctl.t, c->samples, c->sum_e, c->sum_m2, c->sum_m4, out);
+    fill_obs(c->p, row, ctl.t, c->sums, out);
     return SW_OK;
 }
 

@@ -243,7 +243,7 @@ int retire(sw_server* s, Slot& sl) {
     sw_result res{};
     res.tag = sl.req.tag;
     res.status = SW_OK;
-    fill_obs(sl.req.lattice, row, ctl.t, 0, 0.0, 0.0, 0.0, &res.obs);
+    fill_obs(sl.req.lattice, row, ctl.t, Sums{}, &res.obs);
     uint64_t h = 0;
     for (size_t i = 0; i < N; ++i) h += mix64((static_cast<uint64_t>(i) << 8) | static_cast<uint8_t>(s->spins_host[i]));
     res.spin_hash = h;

@@ -155,6 +155,52 @@ def test_measurements(swmc, orc, q, model, T, L, calls):
     assert rel(ob["mean_m4"], (m2 * m2).mean())
     U = (m2 * m2).mean() / m2.mean() ** 2
     assert rel(ob["binder_u"], U)
+    if model == "potts":
+        assert not ob["corr_hist"].any() and ob["mean_g_quarter"] == 0.0
+
+
+# The clock model's correlation function (Sec. 4): exact correlation counts at
+# r = L/4 and L/2 of the final state, G of that state, and the running means
+# and their ratio R, against the oracle sweep by sweep.  q = 2 and 6 take the
+# per-lane bin path, q = 10 the shared-bin path; L = 1030 and 37 give rows
+# that are not a multiple of four sites and displacements that wrap inside a
+# group of four.
+@pytest.mark.parametrize("q,T,L,calls", [
+    (6, 0.9, 48, (40,)), (6, 0.9, 1030, (3,)), (2, 1.2, 37, (20,)), (4, 0.8, 64, (1, 9)),
+    (10, 0.6, 40, (12,)), (6, 1.1, 130, (5,)), (3, 0.7, 45, (8,)),
+])
+def test_clock_correlations(swmc, orc, q, T, L, calls):
+    therm = 6
+    _say(f"[corr] clock q={q} L={L} calls={calls}")
+    lat = swmc.Lattice(L, q, "clock", T=T, seed=77)
+    lat.sweep(therm)
+    for n in calls:
+        lat.sweep(n, measure=True)
+    ob = lat.measure()
+    ch = orc.Chain(L, q, "clock", T=T, seed=77).sweep(therm)
+    g1s, g2s = [], []
+    for _ in range(sum(calls)):
+        ch.sweep(1)
+        c1, c2 = ch.corr_counts()
+        g1s.append(orc.corr_g(L, q, c1))
+        g2s.append(orc.corr_g(L, q, c2))
+    assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+    c1, c2 = ch.corr_counts()
+    assert np.array_equal(ob["corr_hist"][0], c1) and np.array_equal(ob["corr_hist"][1], c2)
+    rel = lambda a, b: abs(a - b) <= 1e-12 * max(1.0, abs(b))
+    assert rel(ob["g_quarter"], g1s[-1]) and rel(ob["g_half"], g2s[-1])
+    m1, m2 = float(np.mean(g1s)), float(np.mean(g2s))
+    assert rel(ob["mean_g_quarter"], m1) and rel(ob["mean_g_half"], m2)
+    assert rel(ob["corr_ratio"], m2 / m1)
+    # a batch replica measures the same
+    b = swmc.Batch([(L, q, "clock", T, 1.0, 77)])
+    b.sweep(therm)
+    b.sweep(sum(calls), measure=True)
+    obb = b.measure(0)
+    assert np.array_equal(obb["corr_hist"], ob["corr_hist"])
+    assert rel(obb["mean_g_quarter"], m1) and rel(obb["corr_ratio"], m2 / m1)
+    b.close()
+    lat.close()
 
 
 @pytest.mark.parametrize("model,q,T,nsw", [("potts", 2, TC2, 3), ("clock", 6, 0.9, 2)])
