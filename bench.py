@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -157,6 +158,44 @@ def bench_batch(args) -> dict:
             "batched_ns_per_update": t_batch * 1e9 / (sites * sweeps), "batched_s": t_batch, "plain_s": t_plain}
 
 
+def bench_labelers(args) -> dict:
+    """The paper's labelers (Sec. 3, label equivalence after Hawick et al. and
+    after Kalentev et al.) against the union-find path: ns per spin update and
+    iterations per sweep for the Ising model at T_c, L = 256 ... 4096 (the
+    sizes of Table 1).  Each lattice is warmed up with the union-find path,
+    then every labeler runs the same number of sweeps from there."""
+    import paper_1202_0635_amd as swmc
+
+    tc = 1.0 / math.log(1.0 + math.sqrt(2.0))
+    rows = []
+    for L in (256, 512, 1024, 2048, 4096):
+        lat = swmc.Lattice(L, 2, "potts", T=tc, seed=2)
+        lat.sweep(args.warmup)
+        lat.measure()  # synchronises
+        row = {"L": L}
+        for name in ("union_find", "kalentev", "hawick"):
+            lat.set_labeler(name)
+            sweeps = args.steps if name == "union_find" else max(5, args.steps // 20)
+            before = lat.labeler_stats()
+            t0 = time.perf_counter()
+            lat.sweep(sweeps)
+            lat.measure()
+            dt = time.perf_counter() - t0
+            after = lat.labeler_stats()
+            row[name] = {"ns_per_update": dt * 1e9 / (L * L * sweeps), "sweeps": sweeps}
+            if name != "union_find":
+                row[name]["iterations_per_sweep"] = (after["iterations"] - before["iterations"]) / sweeps
+            print(f"[labelers] L={L} {name}: {row[name]}", file=sys.stderr, flush=True)
+        lat.close()
+        rows.append(row)
+    big = rows[-1]
+    return {"metric": "labeler ablation: ns per spin update, Ising at T_c (union-find vs the paper's labelers)",
+            "value": big["kalentev"]["ns_per_update"] / big["union_find"]["ns_per_update"], "unit": "x",
+            "higher_is_better": True, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
+            "config": {"workload": "potts2_Tc_L256-4096", "warmup": args.warmup, "steps": args.steps},
+            "rows": rows}
+
+
 def bench_serve(args) -> dict:
     """Request trace (L log-uniform in [128, 2048], Potts q = 2, 3, 4 or clock q = 6,
     T in [0.8, 1.2] T_c, 100-1000 sweeps): capacity from a saturation run, then
@@ -190,7 +229,7 @@ def bench_serve(args) -> dict:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["sweep", "batch", "serve"], default="sweep",
+    ap.add_argument("--mode", choices=["sweep", "batch", "serve", "labelers"], default="sweep",
                     help="sweep: one L=4096 lattice (default); batch: replica mix; serve: request trace")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--requests", type=int, default=2000)
@@ -218,6 +257,9 @@ def main() -> int:
         return 0
     if args.mode == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return 0
+    if args.mode == "labelers":
+        print(json.dumps(bench_labelers(args)), flush=True)
         return 0
 
     import paper_1202_0635_amd as swmc

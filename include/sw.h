@@ -158,6 +158,21 @@ int sw_set_schedule(sw_ctx* c, int32_t merge_tiles);
  * returns it in *merge_tiles.  Allocates a temporary snapshot buffer. */
 int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles);
 
+/* The cluster labeler (Sec. 3).  SW_LABEL_UNION_FIND (default): tile-local
+ * union-find in LDS, then lock-free unions across tile borders.
+ * SW_LABEL_HAWICK and SW_LABEL_KALENTEV: the two label-equivalence labelers the
+ * paper adapts (Sec. 3; Hawick et al. with the temporary array and atomic
+ * minimum, Kalentev et al. with one array and no atomics), iterated until a
+ * scan changes nothing, with the host reading a flag after every iteration as
+ * in the paper.  Kept as an ablation: canonical labels are unique, so every
+ * labeler gives the same chain; only the time differs.  Single-lattice contexts
+ * only; other values: SW_EINVAL. */
+enum { SW_LABEL_UNION_FIND = 0, SW_LABEL_HAWICK = 1, SW_LABEL_KALENTEV = 2 };
+int sw_set_labeler(sw_ctx* c, int32_t labeler);
+/* Label-equivalence iterations run since the context was made (scan passes,
+ * the last of each sweep included) and the sweeps they served. */
+int sw_labeler_stats(sw_ctx* c, uint64_t* iterations, uint64_t* sweeps);
+
 void sw_free(sw_ctx* c);
 const char* sw_strerror(int status);
 const char* sw_last_error(void);

@@ -125,12 +125,26 @@ class Lattice:
         return self._arena[off: off + self.N].view(torch.int8).view(self.L, self.L)
 
     def profile(self) -> dict:
-        names = (ctypes.c_char_p * 8)()
-        launches = (ctypes.c_int64 * 8)()
-        ms = (ctypes.c_double * 8)()
+        names = (ctypes.c_char_p * 16)()
+        launches = (ctypes.c_int64 * 16)()
+        ms = (ctypes.c_double * 16)()
         nk = ctypes.c_int32()
-        check(_lib.lib().sw_profile_read(self._ctx, names, launches, ms, 8, ctypes.byref(nk)), "sw_profile_read")
+        check(_lib.lib().sw_profile_read(self._ctx, names, launches, ms, 16, ctypes.byref(nk)), "sw_profile_read")
         return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(nk.value)}
+
+    LABELERS = {"union_find": 0, "hawick": 1, "kalentev": 2}
+
+    def set_labeler(self, labeler):
+        """Cluster labeler (Sec. 3): "union_find" (default), or the paper's
+        label-equivalence labelers "hawick" and "kalentev" (an ablation)."""
+        code = self.LABELERS[labeler] if isinstance(labeler, str) else int(labeler)
+        check(_lib.lib().sw_set_labeler(self._ctx, code), "sw_set_labeler")
+        return self
+
+    def labeler_stats(self) -> dict:
+        it, sw = ctypes.c_uint64(), ctypes.c_uint64()
+        check(_lib.lib().sw_labeler_stats(self._ctx, ctypes.byref(it), ctypes.byref(sw)), "sw_labeler_stats")
+        return {"iterations": int(it.value), "sweeps": int(sw.value)}
 
     def set_schedule(self, merge_tiles: int):
         check(_lib.lib().sw_set_schedule(self._ctx, int(merge_tiles)), "sw_set_schedule")

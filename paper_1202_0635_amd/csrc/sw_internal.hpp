@@ -59,7 +59,8 @@ struct Control {
     uint64_t target;  // sweeps stop once t reaches this (all ones: never)
     uint32_t mirror;  // clock model: mirror index of the sweep in progress
     uint32_t live;    // the sweep in progress runs (t < target when it started)
-    uint32_t pad[10];
+    uint32_t changed; // label-equivalence labelers: a scan found a smaller label
+    uint32_t pad[9];
 };
 static_assert(sizeof(Control) == 64, "control block is one 64-byte line");
 
@@ -98,6 +99,14 @@ hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s);
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s);
+// The paper's labelers (Sec. 3) as an ablation: bonds only, then label
+// equivalence iterations, then root words at the sites that label themselves.
+enum Labeler { kUnionFind = 0, kHawick = 1, kKalentev = 2 };
+hipError_t launch_bonds_only(const SweepArgs& a, hipStream_t s);
+hipError_t launch_le_init(const SweepArgs& a, uint32_t* R, hipStream_t s);
+// one iteration: scan (+ analysis, + relabel for Hawick et al.)
+hipError_t launch_le_iteration(const SweepArgs& a, int labeler, uint32_t* R, hipStream_t s);
+hipError_t launch_le_roots(const SweepArgs& a, hipStream_t s);
 
 // Workgroups of each launch for one lattice.
 __host__ __device__ inline uint32_t count_blocks(int L) {
@@ -121,7 +130,10 @@ struct BatchLaunch {
 };
 hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint32_t row);
 
-enum KernelId { kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kKFlipBond, kNumKernels };
+enum KernelId {
+    kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kKFlipBond,
+    kKBondsOnly, kKLeIteration, kKLeRoots, kNumKernels
+};
 extern const char* const kKernelNames[kNumKernels];
 
 }  // namespace swmc

@@ -20,8 +20,9 @@
 
 namespace swmc {
 
-const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge", "k_border_merge", "k_flatten",
-                                               "k_flip",       "k_counts",      "k_flip_bond"};
+const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge",   "k_border_merge", "k_flatten",
+                                               "k_flip",       "k_counts",        "k_flip_bond",    "k_bonds_only",
+                                               "k_le_iteration", "k_le_roots"};
 
 namespace {
 
@@ -245,7 +246,7 @@ struct BondShared {
 
 // kFull: the tile lies inside the lattice (no column or row beyond L), which
 // removes the bounds tests from every row.
-template <int kModel, bool kFused, bool kFull>
+template <int kModel, bool kFused, bool kFull, bool kBondsOnly = false>
 __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty, BondShared& sh) {
     constexpr bool kClock = kModel == 1;
     constexpr int RPW = kTileH / kWaves;  // rows per wave
@@ -444,6 +445,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 a.bond_d[wi] = raw_d[ly];
         }
     }
+    if (kBondsOnly) return;  // the label-equivalence labelers start from the bonds alone
     // Border record, bond masks (lane = row of the tile for the column masks).
     if (wave == kWaves - 1) {
         const bool rowok = kFull || lane < nrows;
@@ -597,13 +599,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
 }
 
-template <int kModel, bool kFused>
+template <int kModel, bool kFused, bool kBondsOnly = false>
 __device__ __forceinline__ void bond_tile(const SweepArgs& a, const int tx, const int ty) {
     __shared__ BondShared sh;
     if ((tx + 1) * kTileW <= a.L && (ty + 1) * kTileH <= a.L)
-        bond_local_tile<kModel, kFused, true>(a, tx, ty, sh);
+        bond_local_tile<kModel, kFused, true, kBondsOnly>(a, tx, ty, sh);
     else
-        bond_local_tile<kModel, kFused, false>(a, tx, ty, sh);
+        bond_local_tile<kModel, kFused, false, kBondsOnly>(a, tx, ty, sh);
 }
 
 // Thread g of a launch over the bonds that cross every step-th tile border
@@ -1246,6 +1248,12 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
 
 // Eight waves per SIMD (the scalar registers over the limit spill to vector
 // lanes).
+template <int kModel>
+__global__ void __launch_bounds__(kBlock) k_bonds_only(SweepArgs a) {
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    bond_tile<kModel, false, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+}
+
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     bond_tile<0, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
@@ -1273,6 +1281,99 @@ __global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
 __global__ void __launch_bounds__(kCountThreads) k_counts(SweepArgs a) { counts(a, blockIdx.x, gridDim.x); }
 
 __global__ void __launch_bounds__(kCountSumThreads) k_count_sum(SweepArgs a) { count_sum(a, a.count_row); }
+
+// ---------------------------------------------------------------------------
+// The paper's own labelers (Sec. 3), kept as an ablation of the union-find
+// path.  Label equivalence after Hawick et al.: a scan lowers R[label] to the
+// smallest label among a site's bonded neighbours (atomic minimum), an
+// analysis resolves the chain of R at every site that labels itself, and a
+// relabel sets label <- R[label].  After Kalentev et al.: one array, the scan
+// lowers label[label] without atomics (a lost race is repaired by the next
+// iteration), and the analysis resolves the chain at every site whose label
+// does not label itself.  Every site starts with its own index; the iteration
+// stops when a scan finds no bonded neighbour with a smaller label, and every
+// site then holds the smallest index of its cluster.  Labels never exceed
+// their index, so every chain walk ends.  One thread per site; workgroup
+// (bx, y) takes 256 sites of row y.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool bond_bit(const uint64_t* m, int w64, int x, int y) {
+    return (m[static_cast<size_t>(y) * w64 + (x >> 6)] >> (x & 63)) & 1ull;
+}
+
+__global__ void __launch_bounds__(256) k_le_init(SweepArgs a, uint32_t* R) {
+    const int x = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x), y = static_cast<int>(blockIdx.y);
+    if (x >= a.L) return;
+    const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
+    a.labels[i] = i;
+    if (R) R[i] = i;
+}
+
+template <bool kHawick>
+__global__ void __launch_bounds__(256) k_le_scan(SweepArgs a, uint32_t* R) {
+    const int L = a.L;
+    const int x = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x), y = static_cast<int>(blockIdx.y);
+    if (x >= L) return;
+    const uint32_t row = __umul24(y, L);
+    const uint32_t l = a.labels[row + x];
+    const int xl = (x == 0) ? L - 1 : x - 1, xr = (x + 1 == L) ? 0 : x + 1;
+    const int yu = (y == 0) ? L - 1 : y - 1, yd = (y + 1 == L) ? 0 : y + 1;
+    uint32_t m = l;
+    if (bond_bit(a.bond_r, a.w64, x, y)) m = min(m, a.labels[row + xr]);
+    if (bond_bit(a.bond_r, a.w64, xl, y)) m = min(m, a.labels[row + xl]);
+    if (bond_bit(a.bond_d, a.w64, x, y)) m = min(m, a.labels[__umul24(yd, L) + x]);
+    if (bond_bit(a.bond_d, a.w64, x, yu)) m = min(m, a.labels[__umul24(yu, L) + x]);
+    if (m < l) {
+        if (kHawick)
+            atomicMin(&R[l], m);
+        else if (m < a.labels[l])
+            a.labels[l] = m;
+        a.ctl->changed = 1u;
+    }
+}
+
+// Hawick et al.: a site that labels itself resolves the chain of R from its index.
+__global__ void __launch_bounds__(256) k_le_analysis_r(SweepArgs a, uint32_t* R) {
+    const int x = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x), y = static_cast<int>(blockIdx.y);
+    if (x >= a.L) return;
+    const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
+    if (a.labels[i] != i) return;
+    uint32_t ref = R[i];
+    while (ref != R[ref]) ref = R[ref];
+    R[i] = ref;
+}
+
+__global__ void __launch_bounds__(256) k_le_relabel(SweepArgs a, const uint32_t* R) {
+    const int x = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x), y = static_cast<int>(blockIdx.y);
+    if (x >= a.L) return;
+    const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
+    a.labels[i] = R[a.labels[i]];
+}
+
+// Kalentev et al.: a site whose label does not label itself follows the chain.
+__global__ void __launch_bounds__(256) k_le_analysis(SweepArgs a) {
+    const int x = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x), y = static_cast<int>(blockIdx.y);
+    if (x >= a.L) return;
+    const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
+    uint32_t l = a.labels[i];
+    if (a.labels[l] == l) return;
+    while (l != a.labels[l]) l = a.labels[l];
+    a.labels[i] = l;
+}
+
+// After the last iteration: every site that labels itself (the smallest
+// index of its cluster) receives its cluster's root word, so the flip reads
+// labels exactly as after the union-find path.
+__global__ void __launch_bounds__(256) k_le_roots(SweepArgs a) {
+    const int x = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x), y = static_cast<int>(blockIdx.y);
+    if (x >= a.L) return;
+    const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
+    if (a.labels[i] != i) return;
+    const uint32_t w = draw(i, a.ctl->t, kCluster, a.key0, a.key1).w0;
+    a.labels[i] = kRootFlag | (a.model == 1 ? (w >> 31) : qmap(w, static_cast<uint32_t>(a.q)));
+}
+
+// The sweep index advances once nothing of the sweep reads it any more.
+__global__ void k_le_advance(SweepArgs a) { a.ctl->t += 1; }
 
 struct BatchMap {
     const SweepArgs* reps;  // replica table
@@ -1388,6 +1489,40 @@ hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s) {
         hipLaunchKernelGGL(k_flip<true>, grid, dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_flip<false>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bonds_only(const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
+    if (a.model == 1)
+        hipLaunchKernelGGL(k_bonds_only<1>, grid, dim3(kBlock), cut_bytes(a.q), s, a);
+    else
+        hipLaunchKernelGGL(k_bonds_only<0>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+static dim3 le_grid(const SweepArgs& a) { return dim3(static_cast<unsigned>((a.L + 255) / 256), static_cast<unsigned>(a.L)); }
+
+hipError_t launch_le_init(const SweepArgs& a, uint32_t* R, hipStream_t s) {
+    hipLaunchKernelGGL(k_le_init, le_grid(a), dim3(256), 0, s, a, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_le_iteration(const SweepArgs& a, int labeler, uint32_t* R, hipStream_t s) {
+    if (labeler == kHawick) {
+        hipLaunchKernelGGL(k_le_scan<true>, le_grid(a), dim3(256), 0, s, a, R);
+        hipLaunchKernelGGL(k_le_analysis_r, le_grid(a), dim3(256), 0, s, a, R);
+        hipLaunchKernelGGL(k_le_relabel, le_grid(a), dim3(256), 0, s, a, static_cast<const uint32_t*>(R));
+    } else {
+        hipLaunchKernelGGL(k_le_scan<false>, le_grid(a), dim3(256), 0, s, a, R);
+        hipLaunchKernelGGL(k_le_analysis, le_grid(a), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_le_roots(const SweepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_le_roots, le_grid(a), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_le_advance, dim3(1), dim3(1), 0, s, a);
     return hipGetLastError();
 }
 

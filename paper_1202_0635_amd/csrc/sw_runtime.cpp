@@ -259,6 +259,8 @@ struct sw_ctx {
     // per-kernel timing
     std::vector<hipEvent_t> free_events;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    int labeler = kUnionFind;
+    uint64_t le_iterations = 0, le_sweeps = 0;
     int64_t prof_launches[kNumKernels] = {};
     double prof_ms[kNumKernels] = {};
 };
@@ -433,6 +435,48 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         if (st) return st;
         return row_done();
     };
+    if (c->labeler != kUnionFind) {
+        // The paper's labelers: every sweep is bonds, label equivalence until
+        // a scan changes nothing, root words, flip.
+        SweepArgs a = c->args;
+        uint32_t* R = (c->labeler == kHawick) ? reinterpret_cast<uint32_t*>(c->base + c->lay.labels2) : nullptr;
+        uint32_t* changed = &a.ctl->changed;
+        const int64_t cap = 4ll * c->p.L + 64;  // labels fall at every pass that continues
+        for (int32_t s = 0; s < nsweeps; ++s) {
+            const bool verify = (flags & SW_VERIFY) && s == nsweeps - 1;
+            st = timed(c, profile, kKBondsOnly, [&] { return launch_bonds_only(a, c->stream); });
+            if (st) return st;
+            SW_HIP(c, launch_le_init(a, R, c->stream));
+            int64_t it = 0;
+            for (;;) {
+                SW_HIP(c, hipMemsetAsync(changed, 0, sizeof(uint32_t), c->stream));
+                st = timed(c, profile, kKLeIteration, [&] { return launch_le_iteration(a, c->labeler, R, c->stream); });
+                if (st) return st;
+                uint32_t flag = 0;
+                SW_HIP(c, hipMemcpyAsync(&flag, changed, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+                SW_HIP(c, hipStreamSynchronize(c->stream));
+                ++it;
+                if (!flag) break;
+                if (it >= cap) {
+                    c->sticky = true;
+                    return fail(SW_EDEVICE, "label equivalence did not converge in %lld passes",
+                                static_cast<long long>(cap));
+                }
+            }
+            c->le_iterations += static_cast<uint64_t>(it);
+            c->le_sweeps += 1;
+            st = timed(c, profile, kKLeRoots, [&] { return launch_le_roots(a, c->stream); });
+            if (st) return st;
+            st = timed(c, profile, kKFlip, [&] { return launch_flip(a, verify, c->stream); });
+            if (st) return st;
+            if (verify) c->have_canon = true;
+            if (measure) {
+                st = count_state(a);
+                if (st) return st;
+            }
+        }
+        return flush_ring(c, rows);
+    }
     SweepArgs a = c->args;
     for (int32_t s = 0; s < nsweeps; ++s) {
         const bool last = s == nsweeps - 1;
@@ -586,6 +630,24 @@ int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* to
         c->prof_launches[i] = 0;
         c->prof_ms[i] = 0.0;
     }
+    return SW_OK;
+}
+
+int sw_set_labeler(sw_ctx* c, int32_t labeler) {
+    const int st = check_ctx(c);
+    if (st) return st;
+    if (labeler != SW_LABEL_UNION_FIND && labeler != SW_LABEL_HAWICK && labeler != SW_LABEL_KALENTEV)
+        return fail(SW_EINVAL, "labeler must be SW_LABEL_UNION_FIND, SW_LABEL_HAWICK or SW_LABEL_KALENTEV");
+    c->labeler = labeler;
+    return SW_OK;
+}
+
+int sw_labeler_stats(sw_ctx* c, uint64_t* iterations, uint64_t* sweeps) {
+    const int st = check_ctx(c);
+    if (st) return st;
+    if (!iterations || !sweeps) return fail(SW_EINVAL, "null output pointer");
+    *iterations = c->le_iterations;
+    *sweeps = c->le_sweeps;
     return SW_OK;
 }
 
