@@ -196,6 +196,45 @@ def bench_labelers(args) -> dict:
             "rows": rows}
 
 
+def bench_tscan(args) -> dict:
+    """Temperature dependence of the time per spin update (Figs. 3 and 5: q = 2
+    and q = 3 Potts and the q = 6 clock model at L = 1024), for the union-find
+    path and the label-equivalence labeler of Kalentev et al. (with its
+    iterations per sweep), and for the union-find path at L = 4096."""
+    import paper_1202_0635_amd as swmc
+
+    def run(L, q, model, T, labeler, sweeps):
+        lat = swmc.Lattice(L, q, model, T=T, seed=3)
+        lat.sweep(args.warmup)
+        lat.set_labeler(labeler)
+        lat.measure()
+        before = lat.labeler_stats()
+        t0 = time.perf_counter()
+        lat.sweep(sweeps)
+        lat.measure()
+        dt = time.perf_counter() - t0
+        it = (lat.labeler_stats()["iterations"] - before["iterations"]) / sweeps
+        lat.close()
+        return dt * 1e9 / (L * L * sweeps), it
+
+    rows = []
+    for q, model, tc in ((2, "potts", 1.0 / math.log(1.0 + math.sqrt(2.0))),
+                         (3, "potts", 1.0 / math.log(1.0 + math.sqrt(3.0))), (6, "clock", 0.9)):
+        for f in (0.5, 0.7, 0.85, 0.95, 1.0, 1.05, 1.2, 1.5, 2.0):
+            T = tc * f
+            row = {"model": model, "q": q, "T": T, "T_over_ref": f}
+            row["uf_L1024_ns"], _ = run(1024, q, model, T, "union_find", args.steps)
+            row["kalentev_L1024_ns"], row["kalentev_iterations"] = run(1024, q, model, T, "kalentev",
+                                                                        max(5, args.steps // 20))
+            row["uf_L4096_ns"], _ = run(4096, q, model, T, "union_find", args.steps)
+            print(f"[tscan] {row}", file=sys.stderr, flush=True)
+            rows.append(row)
+    return {"metric": "temperature dependence of ns per spin update (L = 1024 and 4096)", "value": None,
+            "unit": "ns/spin-update", "higher_is_better": False, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
+            "config": {"workload": "tscan_potts2_potts3_clock6", "warmup": args.warmup, "steps": args.steps},
+            "rows": rows}
+
+
 def bench_serve(args) -> dict:
     """Request trace (L log-uniform in [128, 2048], Potts q = 2, 3, 4 or clock q = 6,
     T in [0.8, 1.2] T_c, 100-1000 sweeps): capacity from a saturation run, then
@@ -229,7 +268,7 @@ def bench_serve(args) -> dict:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["sweep", "batch", "serve", "labelers"], default="sweep",
+    ap.add_argument("--mode", choices=["sweep", "batch", "serve", "labelers", "tscan"], default="sweep",
                     help="sweep: one L=4096 lattice (default); batch: replica mix; serve: request trace")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--requests", type=int, default=2000)
@@ -260,6 +299,9 @@ def main() -> int:
         return 0
     if args.mode == "labelers":
         print(json.dumps(bench_labelers(args)), flush=True)
+        return 0
+    if args.mode == "tscan":
+        print(json.dumps(bench_tscan(args)), flush=True)
         return 0
 
     import paper_1202_0635_amd as swmc

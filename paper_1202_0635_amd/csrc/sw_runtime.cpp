@@ -260,6 +260,10 @@ struct sw_ctx {
     std::vector<hipEvent_t> free_events;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     int labeler = kUnionFind;
+    // counts of measured sweeps run on a second stream (made on first use,
+    // default priority), ordered against the sweep by events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_state = nullptr, ev_count[2] = {nullptr, nullptr};
     uint64_t le_iterations = 0, le_sweeps = 0;
     int64_t prof_launches[kNumKernels] = {};
     double prof_ms[kNumKernels] = {};
@@ -316,6 +320,7 @@ int check_ctx(sw_ctx* c) {
 // Fold count rows [0, rows) of the device ring into the running averages.
 int flush_ring(sw_ctx* c, int rows) {
     if (rows <= 0) return SW_OK;
+    if (c->side) SW_HIP(c, hipStreamSynchronize(c->side));
     SW_HIP(c, hipStreamSynchronize(c->stream));
     c->ring_host.resize(static_cast<size_t>(rows) * kRowWords);
     SW_HIP(c, hipMemcpy(c->ring_host.data(), c->base + c->lay.ring, c->ring_host.size() * 8, hipMemcpyDeviceToHost));
@@ -428,11 +433,41 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
     int8_t* const spins1 = reinterpret_cast<int8_t*>(c->base + c->lay.spins2);
     uint32_t* const labels0 = c->args.labels;
     uint32_t* const labels1 = reinterpret_cast<uint32_t*>(c->base + c->lay.labels2);
+    // Union-find path with measurement (not profiled): the count of a state
+    // runs on the side stream after the kernel that wrote the state, and the
+    // next kernel that overwrites that spin buffer (two sweeps later, or the
+    // call's final flip) waits for it, so counting overlaps the merges and
+    // the next sweep's bond kernel.
+    const bool overlap = measure && !profile && c->labeler == kUnionFind;
+    if (overlap && !c->side) {
+        SW_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        SW_HIP(c, hipEventCreateWithFlags(&c->ev_state, hipEventDisableTiming));
+        for (auto& ev : c->ev_count) SW_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    bool pending[2] = {false, false};  // a count of spin buffer 0 / 1 may still run
+    auto buffer_of = [&](const int8_t* p) { return p == spins0 ? 0 : 1; };
+    auto before_write = [&](const int8_t* p) -> int {
+        const int b = buffer_of(p);
+        if (pending[b]) {
+            SW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_count[b], 0));
+            pending[b] = false;
+        }
+        return SW_OK;
+    };
     auto count_state = [&](SweepArgs a) -> int {
         st = next_row(&a.count_row);
         if (st) return st;
-        st = timed(c, profile, kKCounts, [&] { return launch_counts(a, c->stream); });
-        if (st) return st;
+        if (overlap) {
+            SW_HIP(c, hipEventRecord(c->ev_state, c->stream));
+            SW_HIP(c, hipStreamWaitEvent(c->side, c->ev_state, 0));
+            SW_HIP(c, launch_counts(a, c->side));
+            const int b = buffer_of(a.spins);
+            SW_HIP(c, hipEventRecord(c->ev_count[b], c->side));
+            pending[b] = true;
+        } else {
+            st = timed(c, profile, kKCounts, [&] { return launch_counts(a, c->stream); });
+            if (st) return st;
+        }
         return row_done();
     };
     if (c->labeler != kUnionFind) {
@@ -490,6 +525,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
             f.spins_prev = a.spins;
             f.labels = (a.labels == labels0) ? labels1 : labels0;
             f.spins = (a.spins == spins0) ? spins1 : spins0;
+            st = before_write(f.spins);
+            if (st) return st;
             st = timed(c, profile, kKFlipBond, [&] { return launch_flip_bond(f, c->stream); });
             if (st) return st;
             a = f;
@@ -512,6 +549,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         if (last) {
             SweepArgs f = a;
             f.flip_out = spins0;
+            st = before_write(spins0);
+            if (st) return st;
             st = timed(c, profile, kKFlip, [&] { return launch_flip(f, verify, c->stream); });
             if (st) return st;
             if (verify) c->have_canon = true;
@@ -522,6 +561,9 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
             }
         }
     }
+    // later work on the context's stream comes after every count of the call
+    for (int b = 0; b < 2; ++b)
+        if (pending[b]) SW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_count[b], 0));
     return flush_ring(c, rows);
 }
 
@@ -724,6 +766,12 @@ void sw_free(sw_ctx* c) {
         (void)hipEventDestroy(pe.second.second);
     }
     for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipEventDestroy(c->ev_state);
+        for (hipEvent_t e : c->ev_count) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(c->side);
+    }
     if (c->owns) (void)hipFree(c->base);
     delete c;
 }
