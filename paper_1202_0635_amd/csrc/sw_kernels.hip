@@ -1266,11 +1266,36 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
 
-__global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
-    border_merge(a, blockIdx.x * blockDim.x + threadIdx.x);
+// Workgroup order of the border kernels: thread g < nvb * L takes row g % L
+// of vertical border g / L, the rest take the horizontal borders, 256 sites
+// per workgroup.  When every workgroup lies within one border (L a multiple
+// of 256) and both parts split evenly over the eight XCDs, each XCD takes one
+// contiguous band of rows of the vertical borders and one contiguous run of
+// the horizontal ones: the rows whose labels the bond kernel wrote on that
+// XCD (tiles are numbered so that each XCD labels one contiguous run of tile
+// rows), so the label loads of the walks tend to hit its L2.
+__device__ __forceinline__ uint32_t border_block(const SweepArgs& a, int step) {
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    const uint32_t L = static_cast<uint32_t>(a.L);
+    if (L % 256u) return b;
+    const uint32_t nvb = static_cast<uint32_t>((a.tiles_x + step - 1) / step);
+    const uint32_t nhb = static_cast<uint32_t>((a.tiles_y + step - 1) / step);
+    const uint32_t bands = L / 256u;
+    const uint32_t nv = nvb * bands, nh = nhb * bands;
+    if (n != nv + nh || nv % kXcds || nh % kXcds) return b;
+    const uint32_t x = b % kXcds, i = b / kXcds, cv = nv / kXcds;
+    if (i < cv) {
+        const uint32_t v = x * cv + i;  // band-major: band v / nvb, border v % nvb
+        return (v % nvb) * bands + v / nvb;
+    }
+    return nv + x * (nh / kXcds) + (i - cv);
 }
 
-__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
+    border_merge(a, border_block(a, a.merge_tiles) * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, border_block(a, 1)); }
 
 template <bool kVerify>
 __global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
