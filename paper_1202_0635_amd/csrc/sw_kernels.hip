@@ -517,19 +517,24 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
 
     // Phase 2b: vertical bonds between the strips of consecutive waves.  A
     // bond is skipped when the lane to its left carries a vertical bond
-    // between the same two runs.
+    // between the same two runs.  The union starts from the two sites' run
+    // entries (their run's first site, or its label), so the walks touch only
+    // run starts and roots: every other site keeps pointing at its run's
+    // first site, in its own row.
     if (wave + 1 < kWaves) {
         const int ly = ly_base + RPW - 1;
         const uint64_t d = (kFull || y0 + ly + 1 < L) ? raw_d[ly] : 0ull;
         if (((d >> lane) & 1ull) &&
             !(lane > 0 && ((d >> (lane - 1)) & 1ull) && ((raw_r[ly] >> (lane - 1)) & 1ull) &&
               ((raw_r[ly + 1] >> (lane - 1)) & 1ull)))
-            lds_union(P, static_cast<uint32_t>(ly * kTileW + lane), static_cast<uint32_t>((ly + 1) * kTileW + lane));
+            lds_union(P, lds_load(&P[ly * kTileW + lane]), lds_load(&P[(ly + 1) * kTileW + lane]));
     }
     __syncthreads();
 
     // Phase 3: tile-local roots.  Run starts are pointed straight at their
-    // root, after which any site reaches its root in two loads.
+    // root, after which any site reaches its root in two loads.  The walks
+    // only read: a wave stores only into its own run starts, so no store can
+    // replace a root another wave has just placed (a halving store could).
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         if (__builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1))) {
@@ -537,38 +542,55 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
             const uint32_t p = lds_load(&P[self]);
             if (p != self) {
-                const uint32_t gp = lds_load(&P[p]);
-                if (gp != p) lds_store(&P[self], lds_find_from(P, p, gp));
+                uint32_t x = p, gp = lds_load(&P[p]);
+                if (gp != p) {
+                    while (gp != x) {
+                        x = gp;
+                        gp = lds_load(&P[x]);
+                    }
+                    lds_store(&P[self], x);
+                }
             }
         }
     }
+    // From here on every wave reads only its own rows of P: a run's first
+    // site holds its root, any other site points at its run's first site.
     __syncthreads();
     uint32_t rootreg[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
-        rootreg[r] = P[P[self]];
+        const uint32_t p = P[self];
+        rootreg[r] = __builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1)) ? p : P[p];
     }
-    // Border record, edge roots: edge = wave (right column, bottom row, left
-    // column, top row), position = lane.
-    static_assert(kWaves == 4 && kTileW == 64 && kTileH == 64, "one wave per tile edge, one lane per position");
+    // Border record, edge roots (global site indices), from the registers of
+    // the waves that own the rows: right column (edge 0) by the lane of the
+    // last column, left column (edge 2) by lane 0, top row (edge 3) by wave 0,
+    // bottom row (edge 1) by the wave holding row nrows - 1.
     {
-        int ly = lane, lx = lane;
-        bool valid = kFull || lane < nrows;
-        if (wave == 0) lx = nvalid - 1;
-        if (wave == 2) lx = 0;
-        if (wave == 1 || wave == 3) {
-            ly = (wave == 1) ? nrows - 1 : 0;
-            valid = kFull || lane < nvalid;
+        auto global_of = [&](uint32_t root) { return tile_base + __umul24(root >> 6, L) + (root & 63u); };
+        uint32_t* const rec = a.border_roots + tile * 4 * kTileW;
+        if (lane == nvalid - 1 || lane == 0) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r)
+                if (kFull || ly_base + r < nrows) {
+                    const uint32_t g = global_of(rootreg[r]);
+                    if (lane == nvalid - 1) rec[0 * kTileW + ly_base + r] = g;
+                    if (lane == 0) rec[2 * kTileW + ly_base + r] = g;
+                }
         }
-        if (valid) {
-            const uint32_t root = P[P[ly * kTileW + lx]];
-            a.border_roots[(tile * 4 + static_cast<size_t>(wave)) * kTileW + lane] =
-                tile_base + __umul24(root >> 6, L) + (root & 63u);
+        if (lane < nvalid) {
+            if (wave == 0) rec[3 * kTileW + lane] = global_of(rootreg[0]);
+            if (ly_base <= nrows - 1 && nrows - 1 < ly_base + RPW) {
+                uint32_t v = rootreg[0];
+#pragma unroll
+                for (int r = 1; r < RPW; ++r)
+                    if (ly_base + r == nrows - 1) v = rootreg[r];
+                rec[1 * kTileW + lane] = global_of(v);
+            }
         }
     }
-    __syncthreads();
-    uint32_t* list = P + ly_base * kTileW;  // this wave's slice of P holds its root list
+    uint32_t* list = P + ly_base * kTileW;  // this wave's rows of P hold its root list
     uint32_t nroots = 0;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -588,7 +610,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         if (is_root) list[nroots + below] = i;
         nroots += static_cast<uint32_t>(__popcll(rm));
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();  // the list is read by other lanes of this wave only
     // Every tile-local root draws its cluster's value (Sec. 3 assigns a new
     // value to every label index; here only roots draw, one lane per root).
     for (uint32_t j = lane; j < nroots; j += 64) {
