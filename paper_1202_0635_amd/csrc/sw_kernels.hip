@@ -1,20 +1,28 @@
 // HIP kernels of the Swendsen-Wang sweep for gfx950 (wave64, LDS union-find).
 //
-// One sweep = k_bond_local -> k_border_merge -> k_flatten -> k_flip (Sec. 2
-// steps (1)-(3);
-// the GPU organisation of Sec. 3 is replaced by a non-iterative union-find):
-//   k_bond_local   per 64 x kTileH tile: FK bonds from Philox draws, row runs by
-//                  wave ballots, vertical unions in an LDS forest, tile-local
-//                  roots written to the global label forest; every tile-local
-//                  root draws its cluster value now (a root that later loses
-//                  the merge simply never gets read).
-//   k_border_merge one thread per bond that leaves a tile or wraps around the
-//                  torus: lock-free union of the two global roots, the larger
-//                  index linked under the smaller by compare-and-swap.
-//   k_flatten      points every linked tile-local root straight at its root.
-//   k_flip         each site follows its (now at most three-step) path to the
-//                  root word and takes the root's value (Potts) or
-//                  reflection (clock).
+// One sweep (Sec. 2 steps (1)-(3); the GPU organisation of Sec. 3 is replaced
+// by a non-iterative union-find):
+//   k_bond_local    per 64 x 64 tile: FK bonds from Philox draws, row runs by
+//                   wave ballots, a Hoshen-Kopelman pass per wave and unions
+//                   in an LDS forest; tile-local roots written to the global
+//                   label forest with their cluster draw; per-tile border
+//                   records (edge roots and bond masks).
+//   k_flip_bond     the same for every sweep of a call after its first, with
+//                   the previous sweep's flip fused in (spins and labels
+//                   alternate between two buffers).
+//   k_block_merge   (schedules 2 and 4) the inner borders of blocks of tiles,
+//                   joined in LDS.
+//   k_border_merge  the remaining tile borders and the torus wrap: lock-free
+//                   unions of global roots, the larger index linked under the
+//                   smaller by compare-and-swap.
+//   k_flatten       every linked tile-local root gets its cluster's root word
+//                   (or, for a verified sweep, a link straight to the root).
+//   k_flip          the last sweep of a call: each site reaches its root word
+//                   and takes the cluster's value (Potts) or reflection (clock).
+//   k_counts        measured sweeps: n[k], neighbour differences and, for the
+//                   clock model, the correlation counts at L/4 and L/2.
+// The paper's own label-equivalence labelers (k_bonds_only, k_le_*) are kept
+// as an ablation; kb_* are the batched versions (one launch for all replicas).
 #include "sw_device.hpp"
 #include "sw_internal.hpp"
 
