@@ -248,7 +248,6 @@ struct BondShared {
     uint64_t raw_r[kTileH];               // right-bond masks of the tile's rows
     uint64_t raw_d[kTileH];               // down-bond masks
     alignas(16) uint8_t halo[kTileH];     // spins of the column right of the tile
-    uint32_t slot[kWaves][kTileW];        // per-run minimum of the labelling pass
     uint32_t ntie;
 };
 
@@ -486,7 +485,6 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     };
     const uint64_t le_lane = ~0ull >> (63 - lane);  // this lane and the lanes below it
     {
-        uint32_t* my_slot = sh.slot[wave];
         uint32_t lab_prev = kNone;
         uint64_t d_above = 0;  // down bonds of the row above (within the strip)
 #pragma unroll
@@ -503,19 +501,19 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 const uint32_t p = lds_load(&P[lab_prev]);
                 cand = (p == lab_prev) ? p : lds_find_from(P, lab_prev, p);
             }
-            if (run_start) my_slot[lane] = kNone;
+            // every site points at its run's first site; the first site's
+            // entry then takes the smallest root above the run (roots of
+            // earlier rows have smaller indices), which is the run's label
+            P[ly * kTileW + lane] = node;
             __builtin_amdgcn_wave_barrier();
-            if (cand != kNone) atomicMin(&my_slot[start], cand);
+            if (cand != kNone) atomicMin(&P[node], cand);
             __builtin_amdgcn_wave_barrier();
-            const uint32_t m = my_slot[start];
-            const uint32_t lab = (m == kNone) ? node : m;
-            P[ly * kTileW + lane] = run_start ? lab : node;
-            __builtin_amdgcn_wave_barrier();
-            // cand and m were roots when found (m < cand); link cand under m
-            // at once, and join its new parent too if it was linked meanwhile
-            if (cand != kNone && cand != m) {
-                const uint32_t old = __hip_atomic_fetch_min(&P[cand], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (old != cand) lds_union(P, old, m);
+            const uint32_t lab = lds_load(&P[node]);
+            // cand and lab were roots when found (lab < cand); link cand under
+            // lab at once, and join its new parent too if it was linked meanwhile
+            if (cand != kNone && cand != lab) {
+                const uint32_t old = __hip_atomic_fetch_min(&P[cand], lab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old != cand) lds_union(P, old, lab);
             }
             lab_prev = lab;
             d_above = uniform64(raw_d[ly]);
