@@ -245,6 +245,23 @@ def test_full_size_L4096_one_call(swmc, orc, model, q, T):
     lat.close()
 
 
+def test_zero_sweeps_change_nothing(swmc, orc):
+    # a call with no sweeps (with or without measurement) leaves state, sweep
+    # index and running averages as they were
+    lat = swmc.Lattice(70, 3, "potts", T=TC3, seed=8)
+    lat.sweep(3, measure=True)
+    s0, ob0 = lat.spins().copy(), lat.measure()
+    lat.sweep(0)
+    lat.sweep(0, measure=True)
+    ob1 = lat.measure()
+    assert np.array_equal(lat.spins(), s0)
+    assert ob1["t"] == ob0["t"] == 3 and ob1["samples"] == ob0["samples"] == 3
+    assert ob1["mean_e"] == ob0["mean_e"]
+    ch = orc.Chain(70, 3, "potts", T=TC3, seed=8).sweep(3)
+    assert np.array_equal(s0.reshape(-1), ch.spins)
+    lat.close()
+
+
 def test_invalid_arguments_raise(swmc):
     with pytest.raises(swmc.SwError):
         swmc.Lattice(1, 2, "potts", T=1.0)
