@@ -279,6 +279,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="potts2_L4096_Tc")
+    ap.add_argument("--schedule", type=int, choices=[1, 2, 4], default=None,
+                    help="merge schedule of the sweep mode (default: the autotuner's pick)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -313,7 +315,11 @@ def main() -> int:
     lat = swmc.Lattice(cfg.L, cfg.q, cfg.model, T=cfg.T, J=cfg.J, seed=cfg.seed)
     lat.sweep(args.warmup)
     # the autotuner picks the merge schedule on the warmed-up state and restores it
-    schedule = lat.tune(10)
+    if args.schedule is None:
+        schedule = lat.tune(10)
+    else:
+        schedule = args.schedule
+        lat.set_schedule(schedule)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)

@@ -95,9 +95,10 @@ def test_parity_from_arbitrary_state(swmc, orc, L, q, model, T):
     (130, 6, "clock", 0.9, 3, (4, 1)), (127, 2, "potts", 0.5, 13, (4,)), (200, 2, "potts", 5.0, 14, (3,)),
     (192, 32, "potts", 0.4, 15, (3,)), (97, 32, "clock", 0.05, 16, (3,)),
 ])
-def test_multi_sweep_calls(swmc, orc, L, q, model, T, seed, calls):
-    _say(f"[fused] L={L} q={q} {model} calls={calls}")
-    lat = swmc.Lattice(L, q, model, T=T, seed=seed)
+@pytest.mark.parametrize("mt", [4, 1])  # merge schedules: blocks of 4 x 4 tiles first; one border kernel
+def test_multi_sweep_calls(swmc, orc, L, q, model, T, seed, calls, mt):
+    _say(f"[fused] L={L} q={q} {model} calls={calls} schedule={mt}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=seed).set_schedule(mt)
     ch = orc.Chain(L, q, model, T=T, seed=seed)
     for n in calls:
         lat.sweep(n, verify=True)
@@ -219,15 +220,16 @@ def test_full_size_L4096(swmc, orc, model, q, T, nsw):
     lat.close()
 
 
+@pytest.mark.parametrize("mt", [1, 4])  # the autotuner picks schedule 1 at this size
 @pytest.mark.parametrize("model,q,T", [("potts", 2, TC2), ("clock", 6, 0.9)])
-def test_full_size_L4096_one_call(swmc, orc, model, q, T):
+def test_full_size_L4096_one_call(swmc, orc, model, q, T, mt):
     # The benchmark's launch configuration: several sweeps in one call, every
     # sweep after the first running the fused flip-and-bond kernel.  Whole
     # states are compared, with the counts of a measured call and the bonds and
     # canonical labels of a verified one.
     L = 4096
-    _say(f"[full, one call] L=4096 {model} q={q}")
-    lat = swmc.Lattice(L, q, model, T=T, seed=2)
+    _say(f"[full, one call] L=4096 {model} q={q} schedule={mt}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=2).set_schedule(mt)
     ch = orc.Chain(L, q, model, T=T, seed=2)
     lat.sweep(3, measure=True)
     ch.sweep(3)
