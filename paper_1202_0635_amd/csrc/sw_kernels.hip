@@ -334,16 +334,26 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         w[RPW + 1] = halo_lane ? a.labels_prev[ih] : kRootFlag;
         // the previous forest holds root words at its roots and copies of them
         // at its linked tile-local roots, and every other site names its
-        // tile-local root: one more load reaches a root word
+        // tile-local root: one more load reaches a root word.  Every lane
+        // loads (a root word's lane reads site 0 and keeps its own word), so
+        // the RPW + 2 loads are issued back to back and waited for once.
+        uint32_t w2[RPW + 2];
 #pragma unroll
-        for (int r = 0; r <= RPW + 1; ++r)
-            if (!(w[r] & kRootFlag)) w[r] = a.labels_prev[w[r]];
+        for (int r = 0; r <= RPW + 1; ++r) w2[r] = a.labels_prev[(w[r] & kRootFlag) ? 0u : w[r]];
+#pragma unroll
+        for (int r = 0; r <= RPW + 1; ++r) w[r] = (w[r] & kRootFlag) ? w[r] : w2[r];
         if (wave == 0)
             halo[lane] = halo_lane ? static_cast<uint8_t>(flipped<kClock>(w[RPW + 1], kClock ? a.spins_prev[ih] : 0, m_prev, q)) : 0;
+        // clock: the old spins, all loaded before the first store of a new
+        // spin (the two buffers could alias as far as the compiler knows)
+        int sp[RPW + 1];
+#pragma unroll
+        for (int r = 0; r <= RPW; ++r)
+            sp[r] = (kClock && row_ok(r)) ? (a.spins_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0)))[ulane] : 0;
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
             const uint32_t rb = __umul24(row_of(r), L) + static_cast<uint32_t>(x0);
-            sreg[r] = row_ok(r) ? flipped<kClock>(w[r], kClock ? (a.spins_prev + rb)[ulane] : 0, m_prev, q) : 0;
+            sreg[r] = row_ok(r) ? flipped<kClock>(w[r], sp[r], m_prev, q) : 0;
             // the new state of this wave's own rows
             if (r < RPW && (kFull || (col_ok && y_base + r < L))) (a.spins + rb)[ulane] = static_cast<int8_t>(sreg[r]);
         }
