@@ -107,13 +107,13 @@ __device__ __forceinline__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* 
     return x;
 }
 
-// Root of x through ordinary (cached) loads, halving the path on the way.
-// Every word written before this kernel is visible; a word linked meanwhile
-// may be seen stale, which at worst makes the following compare-and-swap
-// fail.  A word read as a non-root can no longer be a root, so the halving
-// stores never touch the root words the compare-and-swap works on.
-__device__ __forceinline__ uint32_t c_find(uint32_t* lab, uint32_t x, uint32_t* word) {
-    uint32_t w = lab[x];
+// Root of x, whose word w the caller has loaded, through ordinary (cached)
+// loads, halving the path on the way.  Every word written before this kernel
+// is visible; a word linked meanwhile may be seen stale, which at worst makes
+// the following compare-and-swap fail.  A word read as a non-root can no
+// longer be a root, so the halving stores never touch the root words the
+// compare-and-swap works on.
+__device__ __forceinline__ uint32_t c_find_from(uint32_t* lab, uint32_t x, uint32_t w, uint32_t* word) {
     while (!(w & kRootFlag)) {
         const uint32_t w2 = lab[w];
         if (w2 & kRootFlag) {
@@ -171,19 +171,19 @@ struct BorderBond {
 __device__ __forceinline__ uint32_t bit(uint64_t m, int k) { return static_cast<uint32_t>(m >> k) & 1u; }
 
 // Right-edge bond of tile column tx in row y (wrapping to column 0 after the
-// last column).
+// last column).  The record words are loaded unconditionally, so their loads
+// are issued together instead of one after another behind each test.
 __device__ __forceinline__ BorderBond vertical_border_bond(const SweepArgs& a, int tx, int y) {
     const int ty = y / kTileH, ly = y - ty * kTileH;
     const int t = ty * a.tiles_x + tx;
     const int tr = ty * a.tiles_x + ((tx + 1 == a.tiles_x) ? 0 : tx + 1);
     const uint64_t* m = a.border_bonds + static_cast<size_t>(t) * kBorderMasks;
-    const uint64_t rr = m[kRightR];
-    if (!bit(rr, ly)) return {false, 0u, 0u};
-    if (ly != 0 && bit(rr, ly - 1) && bit(m[kRightD], ly - 1) &&
-        bit(a.border_bonds[static_cast<size_t>(tr) * kBorderMasks + kLeftD], ly - 1))
-        return {false, 0u, 0u};
-    return {true, a.border_roots[(static_cast<size_t>(t) * 4 + 0) * kTileW + ly],
-            a.border_roots[(static_cast<size_t>(tr) * 4 + 2) * kTileW + ly]};
+    const uint64_t rr = m[kRightR], rd = m[kRightD];
+    const uint64_t ld = a.border_bonds[static_cast<size_t>(tr) * kBorderMasks + kLeftD];
+    const uint32_t i = a.border_roots[(static_cast<size_t>(t) * 4 + 0) * kTileW + ly];
+    const uint32_t j = a.border_roots[(static_cast<size_t>(tr) * 4 + 2) * kTileW + ly];
+    const bool skip = ly != 0 && bit(rr, ly - 1) && bit(rd, ly - 1) && bit(ld, ly - 1);
+    return {bit(rr, ly) && !skip, i, j};
 }
 
 // Bottom-edge bond of tile row ty in column x (wrapping to row 0).
@@ -192,13 +192,12 @@ __device__ __forceinline__ BorderBond horizontal_border_bond(const SweepArgs& a,
     const int t = ty * a.tiles_x + tx;
     const int td = ((ty + 1 == a.tiles_y) ? 0 : ty + 1) * a.tiles_x + tx;
     const uint64_t* m = a.border_bonds + static_cast<size_t>(t) * kBorderMasks;
-    const uint64_t bd = m[kBottomD];
-    if (!bit(bd, lx)) return {false, 0u, 0u};
-    if (lx != 0 && bit(bd, lx - 1) && bit(m[kBottomR], lx - 1) &&
-        bit(a.border_bonds[static_cast<size_t>(td) * kBorderMasks + kTopR], lx - 1))
-        return {false, 0u, 0u};
-    return {true, a.border_roots[(static_cast<size_t>(t) * 4 + 1) * kTileW + lx],
-            a.border_roots[(static_cast<size_t>(td) * 4 + 3) * kTileW + lx]};
+    const uint64_t bd = m[kBottomD], br = m[kBottomR];
+    const uint64_t tr = a.border_bonds[static_cast<size_t>(td) * kBorderMasks + kTopR];
+    const uint32_t i = a.border_roots[(static_cast<size_t>(t) * 4 + 1) * kTileW + lx];
+    const uint32_t j = a.border_roots[(static_cast<size_t>(td) * 4 + 3) * kTileW + lx];
+    const bool skip = lx != 0 && bit(bd, lx - 1) && bit(br, lx - 1) && bit(tr, lx - 1);
+    return {bit(bd, lx) && !skip, i, j};
 }
 
 // ---------------------------------------------------------------------------
@@ -804,8 +803,10 @@ __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t 
     const BorderBond b = border_bond(a, gid, a.merge_tiles);
     uint32_t ra = kRootFlag, rb = kRootFlag, wa = 0, wb = 0;
     if (b.active) {
-        ra = c_find(a.labels, b.i, &wa);
-        rb = c_find(a.labels, b.j, &wb);
+        // the two first loads are issued together; most walks end there
+        const uint32_t wi = a.labels[b.i], wj = a.labels[b.j];
+        ra = c_find_from(a.labels, b.i, wi, &wa);
+        rb = c_find_from(a.labels, b.j, wj, &wb);
         if (ra > rb) {
             uint32_t tmp = ra;
             ra = rb;
@@ -846,8 +847,7 @@ __device__ __forceinline__ void flatten_root(uint32_t* lab, uint32_t r) {
 // written: a halving store could overwrite a copy another thread had just
 // stored.  Every linked node is the end of some border bond, so every one of
 // them is visited.
-__device__ __forceinline__ void copy_root_word(uint32_t* lab, uint32_t r) {
-    uint32_t w = lab[r];
+__device__ __forceinline__ void copy_root_word(uint32_t* lab, uint32_t r, uint32_t w) {
     if (w & kRootFlag) return;  // a cluster root, or a copy already
     do w = lab[w];
     while (!(w & kRootFlag));
@@ -868,8 +868,11 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
     const bool first = (threadIdx.x & 63) == 0;
     const bool do_i = b.active && (first || pi != i), do_j = b.active && (first || pj != j);
     if (a.root_copies) {
-        if (do_i) copy_root_word(a.labels, i);
-        if (do_j) copy_root_word(a.labels, j);
+        // both first loads are issued together (a lane without a walk reads
+        // site 0 and discards it)
+        const uint32_t wi = a.labels[do_i ? i : 0u], wj = a.labels[do_j ? j : 0u];
+        if (do_i) copy_root_word(a.labels, i, wi);
+        if (do_j) copy_root_word(a.labels, j, wj);
     } else {
         if (do_i) flatten_root(a.labels, i);
         if (do_j) flatten_root(a.labels, j);
