@@ -235,6 +235,64 @@ def bench_tscan(args) -> dict:
             "rows": rows}
 
 
+def crossings(temps, curves):
+    """Temperatures where the curves of consecutive sizes cross: for each pair,
+    the sign changes of their difference on the grid, located by linear
+    interpolation (the difference is taken larger size minus smaller)."""
+    sizes = sorted(curves)
+    out = []
+    for a, b in zip(sizes, sizes[1:]):
+        d = [curves[b][k] - curves[a][k] for k in range(len(temps))]
+        for k in range(len(temps) - 1):
+            if d[k] == 0.0 or d[k] * d[k + 1] < 0.0:
+                f = 0.0 if d[k] == 0.0 else d[k] / (d[k] - d[k + 1])
+                out.append({"L_pair": [a, b], "T": temps[k] + f * (temps[k + 1] - temps[k])})
+    return out
+
+
+def bench_uscan(args) -> dict:
+    """Moment ratio U(T) = <M^4>/<M^2>^2 of the q = 2 and q = 3 Potts models
+    (Sec. 4, Fig. 4) and the correlation ratio R(T) = G(L/2)/G(L/4) of the q = 6
+    clock model (Sec. 4, Fig. 6) on a temperature grid for several sizes.  All
+    replicas of a model run in one batch: thermalisation sweeps, then measured
+    sweeps.  For U the crossing temperature of each pair of consecutive sizes
+    is reported beside the exact T_c; the R curves of different sizes coincide
+    between the two KT temperatures and spread outside."""
+    import paper_1202_0635_amd as swmc
+
+    sizes = [int(v) for v in args.uscan_sizes.split(",")]
+    therm, meas = args.uscan_therm, args.uscan_sweeps
+    models = []
+    for q, model, grid in ((2, "potts", [0.97 + 0.0075 * k for k in range(9)]),
+                           (3, "potts", [0.97 + 0.0075 * k for k in range(9)]),
+                           (6, "clock", [0.6 + 0.0625 * k for k in range(9)])):
+        tc = swmc.critical_temperature(model, q)
+        temps = [tc * f for f in grid] if model == "potts" else list(grid)
+        specs = [(L, q, model, T, 1.0, 0x600000 + 1000 * L + k) for L in sizes for k, T in enumerate(temps)]
+        b = swmc.Batch(specs)
+        t0 = time.perf_counter()
+        b.sweep(therm)
+        b.sweep(meas, measure=True)
+        obs = [b.measure(r) for r in range(len(specs))]
+        dt = time.perf_counter() - t0
+        b.close()
+        key = "binder_u" if model == "potts" else "corr_ratio"
+        curves = {L: [obs[i * len(temps) + k][key] for k in range(len(temps))] for i, L in enumerate(sizes)}
+        row = {"model": model, "q": q, "observable": "U" if model == "potts" else "R", "T": temps,
+               "curves": {str(L): c for L, c in curves.items()}, "seconds": dt,
+               "spin_updates": sum(L * L for L in sizes) * len(temps) * (therm + meas)}
+        if model == "potts":
+            row["T_c_exact"] = tc
+            row["crossings"] = crossings(temps, curves)
+        print(f"[uscan] {model} q={q} done in {dt:.1f} s", file=sys.stderr, flush=True)
+        models.append(row)
+    return {"metric": "moment ratio U(T) and correlation ratio R(T) scans", "value": None, "unit": None,
+            "higher_is_better": None, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
+            "config": {"workload": "uscan_potts2_potts3_clock6", "sizes": sizes, "therm_sweeps": therm,
+                       "measured_sweeps": meas},
+            "models": models}
+
+
 def bench_serve(args) -> dict:
     """Request trace (L log-uniform in [128, 2048], Potts q = 2, 3, 4 or clock q = 6,
     T in [0.8, 1.2] T_c, 100-1000 sweeps): capacity from a saturation run, then
@@ -268,13 +326,16 @@ def bench_serve(args) -> dict:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["sweep", "batch", "serve", "labelers", "tscan"], default="sweep",
+    ap.add_argument("--mode", choices=["sweep", "batch", "serve", "labelers", "tscan", "uscan"], default="sweep",
                     help="sweep: one L=4096 lattice (default); batch: replica mix; serve: request trace")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gib", type=float, default=2.0)
     ap.add_argument("--slots", type=int, default=128)
     ap.add_argument("--sweeps-per-step", type=int, default=25)
+    ap.add_argument("--uscan-sizes", default="32,64,128")
+    ap.add_argument("--uscan-therm", type=int, default=2000)
+    ap.add_argument("--uscan-sweeps", type=int, default=20000)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
@@ -304,6 +365,9 @@ def main() -> int:
         return 0
     if args.mode == "tscan":
         print(json.dumps(bench_tscan(args)), flush=True)
+        return 0
+    if args.mode == "uscan":
+        print(json.dumps(bench_uscan(args)), flush=True)
         return 0
 
     import paper_1202_0635_amd as swmc
