@@ -198,9 +198,12 @@ def bench_labelers(args) -> dict:
 
 def bench_tscan(args) -> dict:
     """Temperature dependence of the time per spin update (Figs. 3 and 5: q = 2
-    and q = 3 Potts and the q = 6 clock model at L = 1024), for the union-find
-    path and the label-equivalence labeler of Kalentev et al. (with its
-    iterations per sweep), and for the union-find path at L = 4096."""
+    and q = 3 Potts and the q = 6 clock model at L = 1024; also q = 4 Potts and
+    the q = 32 clock model, close to the XY model), for the union-find path and
+    the label-equivalence labeler of Kalentev et al. (with its iterations per
+    sweep), and for the union-find path at L = 4096.  Temperatures are given
+    relative to T_c (Potts) or to 0.9 (clock models, near the upper KT
+    temperature of q = 6 and the XY model's)."""
     import paper_1202_0635_amd as swmc
 
     def run(L, q, model, T, labeler, sweeps):
@@ -219,7 +222,8 @@ def bench_tscan(args) -> dict:
 
     rows = []
     for q, model, tc in ((2, "potts", 1.0 / math.log(1.0 + math.sqrt(2.0))),
-                         (3, "potts", 1.0 / math.log(1.0 + math.sqrt(3.0))), (6, "clock", 0.9)):
+                         (3, "potts", 1.0 / math.log(1.0 + math.sqrt(3.0))),
+                         (4, "potts", 1.0 / math.log(3.0)), (6, "clock", 0.9), (32, "clock", 0.9)):
         for f in (0.5, 0.7, 0.85, 0.95, 1.0, 1.05, 1.2, 1.5, 2.0):
             T = tc * f
             row = {"model": model, "q": q, "T": T, "T_over_ref": f}
@@ -231,7 +235,7 @@ def bench_tscan(args) -> dict:
             rows.append(row)
     return {"metric": "temperature dependence of ns per spin update (L = 1024 and 4096)", "value": None,
             "unit": "ns/spin-update", "higher_is_better": False, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
-            "config": {"workload": "tscan_potts2_potts3_clock6", "warmup": args.warmup, "steps": args.steps},
+            "config": {"workload": "tscan_potts2_potts3_potts4_clock6_clock32", "warmup": args.warmup, "steps": args.steps},
             "rows": rows}
 
 
