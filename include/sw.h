@@ -153,6 +153,11 @@ int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* to
  * one workgroup, in LDS.  Other values: SW_EINVAL.  Results do not depend on it
  * (canonical labels are unique); only the time does. */
 int sw_set_schedule(sw_ctx* c, int32_t merge_tiles);
+/* Waves per 64 x 64 tile of the bond kernel: 4 (16 rows each) or 8 (8 rows
+ * each).  The default is 8 for lattices of fewer than 3072 tiles (L <= 3520),
+ * where 4-wave workgroups leave the chip's SIMDs short of waves, else 4.
+ * Other values: SW_EINVAL.  Results do not depend on it; only the time does. */
+int sw_set_tile_waves(sw_ctx* c, int32_t waves);
 /* Autotuner: times `sweeps` sweeps under every schedule from the current state,
  * restores the state (spins and sweep index) after each, keeps the fastest and
  * returns it in *merge_tiles.  Allocates a temporary snapshot buffer. */

@@ -150,6 +150,11 @@ class Lattice:
         check(_lib.lib().sw_set_schedule(self._ctx, int(merge_tiles)), "sw_set_schedule")
         return self
 
+    def set_tile_waves(self, waves: int):
+        """Waves per 64 x 64 tile of the bond kernel (4 or 8); results do not depend on it."""
+        check(_lib.lib().sw_set_tile_waves(self._ctx, int(waves)), "sw_set_tile_waves")
+        return self
+
     def tune(self, sweeps: int = 5) -> int:
         out = ctypes.c_int32()
         check(_lib.lib().sw_tune(self._ctx, int(sweeps), ctypes.byref(out)), "sw_tune")

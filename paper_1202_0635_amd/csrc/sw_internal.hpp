@@ -14,6 +14,10 @@ constexpr int kTileW = 64;
 constexpr int kTileH = 64;
 constexpr int kWaves = 4;
 constexpr int kBlock = kWaves * 64;
+// Lattices with fewer tiles than kSmallTiles split each tile over
+// kWavesSmall waves of 8 rows instead, for more waves per CU.
+constexpr int kWavesSmall = 8;
+constexpr int kSmallTiles = 3072;
 // Merge schedule (a per-context parameter, see the autotuner): 1 runs one
 // device-wide border kernel; 2 or 4 first join the inner borders of blocks of
 // that many tiles per side inside one workgroup (in LDS).
@@ -81,6 +85,8 @@ struct SweepArgs {
     uint64_t* border_bonds;   // [tiles][kBorderMasks]: the bond bits the border joins read
     int L, q, model, w64;
     int tiles_x, tiles_y;
+    int tile_waves;       // waves per bond-kernel workgroup: kWaves or kWavesSmall (single
+                          // lattices; batched launches always use kWaves)
     int merge_tiles;      // tiles per side of a first-level merge block (1: no block level)
     int root_copies;      // k_flatten stores the cluster's root word (not a link) at every linked
                           // tile-local root: the labels then lead to a root word in at most two

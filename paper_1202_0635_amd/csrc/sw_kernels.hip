@@ -252,10 +252,10 @@ struct BondShared {
 
 // kFull: the tile lies inside the lattice (no column or row beyond L), which
 // removes the bounds tests from every row.
-template <int kModel, bool kFused, bool kFull, bool kBondsOnly = false>
+template <int kModel, bool kFused, bool kFull, bool kBondsOnly, int kW>
 __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty, BondShared& sh) {
     constexpr bool kClock = kModel == 1;
-    constexpr int RPW = kTileH / kWaves;  // rows per wave
+    constexpr int RPW = kTileH / kW;  // rows per wave (kW waves per tile)
     static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
     uint32_t* const P = sh.P;
     uint64_t* const raw_r = sh.raw_r;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     if (kClock) {
         const int m = mirror_of(t, q, k0, k1);
         const uint32_t* src = a.table + static_cast<size_t>(m) * q * q;
-        for (int k = threadIdx.x; k < q * q; k += kBlock) cut[k] = src[k];
+        for (int k = threadIdx.x; k < q * q; k += kW * 64) cut[k] = src[k];
         if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->mirror = static_cast<uint32_t>(m);
     }
     if (threadIdx.x == 0) ntie = 0;
@@ -368,7 +368,9 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // Phase 1: decisions on the high bytes; ties go to the list.  The right
     // neighbour comes from the next lane by a DPP wave shift; the edge lane
     // takes it from the halo, whose RPW bytes for this wave are read once.
-    const uint4 hv = *reinterpret_cast<const uint4*>(&halo[ly_base]);
+    uint32_t hv[RPW / 4];  // four rows' halo bytes per word
+#pragma unroll
+    for (int k = 0; k < RPW / 4; ++k) hv[k] = *reinterpret_cast<const uint32_t*>(&halo[ly_base + 4 * k]);
     const uint32_t chi = c_eq >> 24;                    // Potts: high byte of the cutoff
     const bool lo_matters = (c_eq & 0xFFFFFFu) != 0u;   // ties need the low 24 bits
 #pragma unroll
@@ -385,7 +387,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             const int s = sreg[r];
             const int sd = sreg[r + 1];
             const int sr_next = __builtin_amdgcn_mov_dpp(s, 0x130, 0xF, 0xF, false);  // wave_shl:1, lane i <- i+1
-            const uint32_t hword = (r < 4) ? hv.x : (r < 8) ? hv.y : (r < 12) ? hv.z : hv.w;
+            const uint32_t hword = hv[r >> 2];
             const int sr = edge_lane ? static_cast<int>((hword >> (8 * (r & 3))) & 0xFFu) : sr_next;
             const uint32_t word = (k < 2) ? hi.w0 : (k < 4) ? hi.w1 : (k < 6) ? hi.w2 : hi.w3;
             const uint32_t hr = (k & 1) ? ((word >> 8) & 0xFFu) : (word >> 24);
@@ -422,7 +424,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
 
     // Phase 1b: ties resolved by the low 24 bits of the per-site draw.
     const uint32_t nt = ntie;
-    for (uint32_t j = threadIdx.x; j < nt; j += kBlock) {
+    for (uint32_t j = threadIdx.x; j < nt; j += kW * 64) {
         const uint32_t e = P[j];
         const int ly = static_cast<int>((e & 0xFFFu) >> 6), lx = static_cast<int>(e & 63u);
         const int y = y0 + ly, xx = x0 + lx;
@@ -463,7 +465,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
     if (kBondsOnly) return;  // the label-equivalence labelers start from the bonds alone
     // Border record, bond masks (lane = row of the tile for the column masks).
-    if (wave == kWaves - 1) {
+    if (wave == kW - 1) {
         const bool rowok = kFull || lane < nrows;
         const uint64_t rr = raw_r[lane], dd = raw_d[lane];
         const uint64_t right_r = __ballot(rowok && ((rr >> (nvalid - 1)) & 1ull));
@@ -536,7 +538,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // entries (their run's first site, or its label), so the walks touch only
     // run starts and roots: every other site keeps pointing at its run's
     // first site, in its own row.
-    if (wave + 1 < kWaves) {
+    if (wave + 1 < kW) {
         const int ly = ly_base + RPW - 1;
         const uint64_t d = (kFull || y0 + ly + 1 < L) ? raw_d[ly] : 0ull;
         if (((d >> lane) & 1ull) &&
@@ -636,13 +638,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
 }
 
-template <int kModel, bool kFused, bool kBondsOnly = false>
+template <int kModel, bool kFused, bool kBondsOnly, int kW>
 __device__ __forceinline__ void bond_tile(const SweepArgs& a, const int tx, const int ty) {
     __shared__ BondShared sh;
     if ((tx + 1) * kTileW <= a.L && (ty + 1) * kTileH <= a.L)
-        bond_local_tile<kModel, kFused, true, kBondsOnly>(a, tx, ty, sh);
+        bond_local_tile<kModel, kFused, true, kBondsOnly, kW>(a, tx, ty, sh);
     else
-        bond_local_tile<kModel, kFused, false, kBondsOnly>(a, tx, ty, sh);
+        bond_local_tile<kModel, kFused, false, kBondsOnly, kW>(a, tx, ty, sh);
 }
 
 // Thread g of a launch over the bonds that cross every step-th tile border
@@ -1281,10 +1283,12 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
     return (n % kXcds) ? b : (b % kXcds) * (n / kXcds) + b / kXcds;
 }
 
-template <int kModel>
-__global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
+// kW waves per tile: 4 (16 rows each) for large lattices, 8 (8 rows each)
+// where the lattice has too few tiles to fill the chip with 4-wave workgroups.
+template <int kModel, int kW>
+__global__ void __launch_bounds__(kW * 64) k_bond_local(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<kModel, false>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<kModel, false, false, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 // Eight waves per SIMD (the scalar registers over the limit spill to vector
@@ -1292,17 +1296,19 @@ __global__ void __launch_bounds__(kBlock) k_bond_local(SweepArgs a) {
 template <int kModel>
 __global__ void __launch_bounds__(kBlock) k_bonds_only(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<kModel, false, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<kModel, false, true, kWaves>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
+template <int kW>
+__global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<0, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<0, true, false, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_clock(SweepArgs a) {
+template <int kW>
+__global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_clock(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<1, true>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<1, true, false, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
@@ -1457,7 +1463,7 @@ template <int kModel>
 __global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    bond_tile<kModel, false>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+    bond_tile<kModel, false, false, kWaves>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
@@ -1509,21 +1515,33 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
+template <int kW>
+static void launch_bond_tiles(const SweepArgs& a, bool fused, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
-    if (a.model == 1)
-        hipLaunchKernelGGL(k_bond_local<1>, grid, dim3(kBlock), cut_bytes(a.q), s, a);
+    const dim3 block(kW * 64);
+    if (fused && a.model == 1)
+        hipLaunchKernelGGL(k_flip_bond_clock<kW>, grid, block, cut_bytes(a.q), s, a);
+    else if (fused)
+        hipLaunchKernelGGL(k_flip_bond_potts<kW>, grid, block, 0, s, a);
+    else if (a.model == 1)
+        hipLaunchKernelGGL((k_bond_local<1, kW>), grid, block, cut_bytes(a.q), s, a);
     else
-        hipLaunchKernelGGL(k_bond_local<0>, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_bond_local<0, kW>), grid, block, 0, s, a);
+}
+
+hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
+    if (a.tile_waves == kWavesSmall)
+        launch_bond_tiles<kWavesSmall>(a, false, s);
+    else
+        launch_bond_tiles<kWaves>(a, false, s);
     return hipGetLastError();
 }
 
 hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
-    if (a.model == 1)
-        hipLaunchKernelGGL(k_flip_bond_clock, grid, dim3(kBlock), cut_bytes(a.q), s, a);
+    if (a.tile_waves == kWavesSmall)
+        launch_bond_tiles<kWavesSmall>(a, true, s);
     else
-        hipLaunchKernelGGL(k_flip_bond_potts, grid, dim3(kBlock), 0, s, a);
+        launch_bond_tiles<kWaves>(a, true, s);
     return hipGetLastError();
 }
 

@@ -205,6 +205,7 @@ SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     a.w64 = (p.L + 63) / 64;
     a.tiles_x = (p.L + kTileW - 1) / kTileW;
     a.tiles_y = (p.L + kTileH - 1) / kTileH;
+    a.tile_waves = (a.tiles_x * a.tiles_y < kSmallTiles) ? kWavesSmall : kWaves;
     a.merge_tiles = kMergeTiles;
     a.key0 = static_cast<uint32_t>(p.seed);
     a.key1 = static_cast<uint32_t>(p.seed >> 32);
@@ -690,6 +691,14 @@ int sw_labeler_stats(sw_ctx* c, uint64_t* iterations, uint64_t* sweeps) {
     if (!iterations || !sweeps) return fail(SW_EINVAL, "null output pointer");
     *iterations = c->le_iterations;
     *sweeps = c->le_sweeps;
+    return SW_OK;
+}
+
+int sw_set_tile_waves(sw_ctx* c, int32_t waves) {
+    const int st = check_ctx(c);
+    if (st) return st;
+    if (waves != kWaves && waves != kWavesSmall) return fail(SW_EINVAL, "waves per tile must be 4 or 8");
+    c->args.tile_waves = waves;
     return SW_OK;
 }
 

@@ -247,6 +247,26 @@ def test_full_size_L4096_one_call(swmc, orc, model, q, T, mt):
     lat.close()
 
 
+@pytest.mark.parametrize("L,q,model,T,seed", [
+    (2, 2, "potts", TC2, 5), (70, 3, "potts", TC3, 6), (130, 6, "clock", 0.9, 3), (300, 2, "potts", TC2, 7),
+    (127, 2, "potts", 0.5, 13),
+])
+@pytest.mark.parametrize("waves", [4, 8])
+def test_tile_waves_do_not_change_results(swmc, orc, L, q, model, T, seed, waves):
+    # 4 waves of 16 rows or 8 waves of 8 rows per tile: the same bonds, labels and spins
+    _say(f"[tile waves] L={L} q={q} {model} waves={waves}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=seed).set_tile_waves(waves)
+    ch = orc.Chain(L, q, model, T=T, seed=seed)
+    for n in (1, 4):
+        lat.sweep(n, verify=True)
+        ch.sweep(n)
+        br, bd = lat.bonds()
+        assert np.array_equal(br.reshape(-1), ch.bond_r) and np.array_equal(bd.reshape(-1), ch.bond_d)
+        assert np.array_equal(lat.labels().reshape(-1), ch.labels)
+        assert np.array_equal(lat.spins().reshape(-1), ch.spins)
+    lat.close()
+
+
 def test_zero_sweeps_change_nothing(swmc, orc):
     # a call with no sweeps (with or without measurement) leaves state, sweep
     # index and running averages as they were
@@ -279,3 +299,6 @@ def test_invalid_arguments_raise(swmc):
     for mt in (0, 3, 8):
         with pytest.raises(swmc.SwError):
             lat.set_schedule(mt)
+    for w in (0, 2, 5, 16):
+        with pytest.raises(swmc.SwError):
+            lat.set_tile_waves(w)
