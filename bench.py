@@ -265,10 +265,10 @@ def bench_uscan(args) -> dict:
     import paper_1202_0635_amd as swmc
 
     sizes = [int(v) for v in args.uscan_sizes.split(",")]
-    therm, meas = args.uscan_therm, args.uscan_sweeps
+    therm, meas, w = args.uscan_therm, args.uscan_sweeps, args.uscan_width
+    potts_grid = [1.0 - w + 0.25 * w * k for k in range(9)]  # T / T_c
     models = []
-    for q, model, grid in ((2, "potts", [0.97 + 0.0075 * k for k in range(9)]),
-                           (3, "potts", [0.97 + 0.0075 * k for k in range(9)]),
+    for q, model, grid in ((2, "potts", potts_grid), (3, "potts", potts_grid),
                            (6, "clock", [0.6 + 0.0625 * k for k in range(9)])):
         tc = swmc.critical_temperature(model, q)
         temps = [tc * f for f in grid] if model == "potts" else list(grid)
@@ -276,7 +276,12 @@ def bench_uscan(args) -> dict:
         b = swmc.Batch(specs)
         t0 = time.perf_counter()
         b.sweep(therm)
-        b.sweep(meas, measure=True)
+        chunk = 10000
+        for done in range(0, meas, chunk):
+            b.sweep(min(chunk, meas - done), measure=True)
+            b.measure(0)  # waits for the chunk
+            print(f"[uscan] {model} q={q}: {min(done + chunk, meas)} of {meas} measured sweeps", file=sys.stderr,
+                  flush=True)
         obs = [b.measure(r) for r in range(len(specs))]
         dt = time.perf_counter() - t0
         b.close()
@@ -293,7 +298,7 @@ def bench_uscan(args) -> dict:
     return {"metric": "moment ratio U(T) and correlation ratio R(T) scans", "value": None, "unit": None,
             "higher_is_better": None, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
             "config": {"workload": "uscan_potts2_potts3_clock6", "sizes": sizes, "therm_sweeps": therm,
-                       "measured_sweeps": meas},
+                       "measured_sweeps": meas, "potts_grid_half_width": w},
             "models": models}
 
 
@@ -340,6 +345,7 @@ def main() -> int:
     ap.add_argument("--uscan-sizes", default="32,64,128")
     ap.add_argument("--uscan-therm", type=int, default=2000)
     ap.add_argument("--uscan-sweeps", type=int, default=20000)
+    ap.add_argument("--uscan-width", type=float, default=0.03, help="Potts grid: T/T_c from 1 - w to 1 + w")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
