@@ -87,12 +87,12 @@ __device__ __forceinline__ void g_store(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root of x in the global forest; *word receives the root word.  Path
-// halving: a visited non-root is pointed at its grandparent.  Only non-root
-// words are rewritten and only with an ancestor's index, so a concurrent
-// compare-and-swap (which targets root words) is never disturbed.
-__device__ __forceinline__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* word) {
-    uint32_t w = g_load(&lab[x]);
+// Root of x in the global forest, from x's word w (read coherently by the
+// caller); *word receives the root word.  Path halving: a visited non-root
+// is pointed at its grandparent.  Only non-root words are rewritten and only
+// with an ancestor's index, so a concurrent compare-and-swap (which targets
+// root words) is never disturbed.
+__device__ __forceinline__ uint32_t g_find_from(uint32_t* lab, uint32_t x, uint32_t w, uint32_t* word) {
     while (!(w & kRootFlag)) {
         const uint32_t w2 = g_load(&lab[w]);
         if (w2 & kRootFlag) {
@@ -146,8 +146,11 @@ __device__ void g_union_roots(uint32_t* lab, uint32_t a, uint32_t wa, uint32_t b
         if (__hip_atomic_compare_exchange_strong(&lab[b], &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return;
-        b = g_find(lab, b, &wb);
-        a = g_find(lab, a, &wa);
+        // the failed swap returned b's current word; a's first load is
+        // issued before b's walk goes on
+        const uint32_t wa0 = g_load(&lab[a]);
+        b = g_find_from(lab, b, expected, &wb);
+        a = g_find_from(lab, a, wa0, &wa);
     }
 }
 
