@@ -26,7 +26,8 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, 8 TB/s
 PAPER_NS_PER_UPDATE = {"potts2_L4096_Tc": 2.51, "clock6_L4096_T0.9": 2.42}  # GTX580, Tables 1 and 3
 
 
-def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile_h: int = 64) -> float:
+def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile_h: int = 64,
+                         merge_tiles: int = 1) -> float:
     """Algorithmic HBM bytes of one launch (the method's own traffic, perf mode).
 
     k_bond_local: spins read once (1 B/site) plus the halo column and row of
@@ -44,11 +45,12 @@ def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile
     if kernel == "k_bond_local":
         return N * (1.0 + 1.0 / tile_w + 1.0 / tile_h + 0.25 + 4.0)
     if kernel in ("k_block_merge", "k_border_merge", "k_flatten"):
+        mt = merge_tiles
         tiles = (-(-L // tile_w)) + (-(-L // tile_h))
-        if kernel == "k_border_merge":   # block borders only (every 4th tile border, and the wrap)
-            tiles = (-(-L // (4 * tile_w))) + (-(-L // (4 * tile_h)))
-        elif kernel == "k_block_merge":
-            tiles -= (-(-L // (4 * tile_w))) + (-(-L // (4 * tile_h)))
+        if kernel == "k_border_merge":   # block borders only (every mt-th tile border, and the wrap)
+            tiles = (-(-L // (mt * tile_w))) + (-(-L // (mt * tile_h)))
+        elif kernel == "k_block_merge":  # the borders inside the blocks (none for mt = 1)
+            tiles -= (-(-L // (mt * tile_w))) + (-(-L // (mt * tile_h)))
         return L * tiles * (0.125 + 8.0)
     if kernel == "k_flip":
         return N * (4.0 + 1.0 + (1.0 if model == "clock" else 0.0))
@@ -60,6 +62,8 @@ def alg_bytes_per_launch(kernel: str, L: int, model: str, tile_w: int = 64, tile
     raise KeyError(kernel)
 
 
+# the kernels of one sweep inside a multi-sweep call
+SWEEP_KERNELS = ("k_flip_bond", "k_block_merge", "k_border_merge", "k_flatten")
 COPY_BYTES = 256 << 20
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1202_0635_amd", "csrc", f)
@@ -97,6 +101,43 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+def _profile_fields(path: str) -> dict:
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    return fields
+
+
+def traced_avg_us(kernel: str, workload: str):
+    """Average duration (us) of `kernel` in the committed rocprofv3 kernel
+    trace (profiles/kernel_trace_<workload>.md), or None when there is none or
+    the kernel sources changed since the trace was taken."""
+    path = os.path.join(PROFILES, f"kernel_trace_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = _profile_fields(path)
+    if fields.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(fields[f"avg_us {kernel}"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, budget_s: float) -> dict:
     """The oracle (single thread) on the first sweeps of the same workload."""
     import oracle
@@ -111,7 +152,8 @@ def cpu_baseline(cfg, budget_s: float) -> dict:
             break
     dt = time.perf_counter() - t0
     return {"value": dt * 1e9 / (n * cfg.L * cfg.L), "unit": "ns/spin-update", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} sweeps of {cfg.name} from the random start (single-threaded C oracle)"}
+            "sample": f"first {n} sweeps of {cfg.name} from the random start (single-threaded C oracle)",
+            "cpu_model": cpu_model(), "oracle_build": oracle.BUILD_FLAGS}
 
 
 def bench_batch(args) -> dict:
@@ -354,6 +396,7 @@ def main() -> int:
                     help="merge schedule of the sweep mode (default: the autotuner's pick)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain replica measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -387,8 +430,11 @@ def main() -> int:
     torch.cuda.set_device(0)
     N = cfg.L * cfg.L
     lat = swmc.Lattice(cfg.L, cfg.q, cfg.model, T=cfg.T, J=cfg.J, seed=cfg.seed)
-    lat.sweep(args.warmup)
-    # the autotuner picks the merge schedule on the warmed-up state and restores it
+    # the workload's thermalisation (200 sweeps for the L = 4096 workloads), or
+    # more if --warmup asks for it, before anything is timed
+    therm = max(args.warmup, cfg.therm)
+    lat.sweep(therm)
+    # the autotuner picks the merge schedule on the thermalised state and restores it
     if args.schedule is None:
         schedule = lat.tune(10)
     else:
@@ -421,10 +467,12 @@ def main() -> int:
     n_c, t_c = lat.profile().get("k_counts", (0, 0.0))
     count_us = 1e3 * t_c / n_c if n_c else None
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-    dom_bytes = alg_bytes_per_launch(dom, cfg.L, cfg.model)
+    bytes_of = lambda k: alg_bytes_per_launch(k, cfg.L, cfg.model, merge_tiles=schedule)
+    dom_bytes = bytes_of(dom)
     achieved = dom_bytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-    # a sweep inside a multi-sweep call: the fused kernel and the merges
-    sweep_bytes = sum(alg_bytes_per_launch(k, cfg.L, cfg.model) for k in ("k_flip_bond", "k_block_merge", "k_border_merge", "k_flatten"))
+    # a sweep inside a multi-sweep call: the fused kernel and the merges that ran
+    sweep_kernels = [k for k in SWEEP_KERNELS if k in kernels]
+    sweep_bytes = sum(bytes_of(k) for k in sweep_kernels)
     sweep_gbps = sweep_bytes / (ms * 1e-3 / args.steps) / 1e9
 
     paper = PAPER_NS_PER_UPDATE.get(cfg.name)
@@ -442,29 +490,47 @@ def main() -> int:
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": cfg.name, "L": cfg.L, "q": cfg.q, "model": cfg.model, "T": cfg.T, "J": cfg.J,
-                   "seed": cfg.seed, "warmup_sweeps": args.warmup, "timed_sweeps": args.steps,
-                   "merge_tiles": schedule},
+                   "seed": cfg.seed, "thermalisation_sweeps": therm, "workload_thermalisation": cfg.therm,
+                   "timed_sweeps": args.steps, "merge_tiles": schedule},
         "spin_updates_per_s": N * args.steps / (ms * 1e-3),
         "ns_per_update_with_measurement": ms_measure * 1e6 / (args.steps * N),
         "k_counts_avg_us": count_us,
+        "sweep_alg_bytes": sweep_bytes,
         "sweep_alg_GBps": sweep_gbps,
+        "sweep_hbm_frac": sweep_gbps / HBM_PEAK_GBPS,
         "kernels": kernels,
+        # the dominant kernel: algorithmic bytes per launch over its HIP-event
+        # average (events bracket every launch, so this average includes the
+        # gap between launches); frac_rocprof uses the committed rocprofv3
+        # trace average of the same kernel when its sources are unchanged
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "alg_bytes_per_launch": dom_bytes,
+                     "hip_event_avg_us": kernels[dom]["avg_us"]},
     }
     traffic = measured_traffic(dom, cfg.name)
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
+    trace_us = traced_avg_us(dom, cfg.name)
+    if trace_us is not None:
+        out["roofline"]["rocprof_avg_us"] = trace_us
+        out["roofline"]["frac_rocprof"] = dom_bytes / (trace_us * 1e-6) / 1e9 / HBM_PEAK_GBPS
+    lat.close()
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if not args.no_batch:
+        # the replica mix, batched against one lattice per launch (500 sweeps)
+        bargs = argparse.Namespace(replicas=256, steps=500, warmup=20)
+        bb = bench_batch(bargs)
+        out["batched_vs_plain"] = {k: bb[k] for k in ("value", "config", "batched_spin_updates_per_s",
+                                                      "plain_spin_updates_per_s", "batched_s", "plain_s")}
+        out["batched_vs_plain"]["sweeps"] = bargs.steps
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    lat.close()
     return 0
 
 

@@ -58,7 +58,8 @@ enum {
     SW_MEASURE = 1u, /* accumulate E, M^2, M^4 after every sweep of this call */
     SW_VERIFY = 2u,  /* also store the canonical labels of the last sweep */
     SW_PROFILE = 4u, /* time every kernel launch with HIP events (read by sw_profile_read) */
-    SW_NO_GRAPH = 8u /* batches: launch the kernels directly instead of replaying the captured sweep */
+    SW_NO_GRAPH = 8u, /* batches: launch the kernels directly instead of replaying the captured sweep */
+    SW_HASH = 16u     /* record the state hashes of every sweep (read by sw_read_hashes) */
 };
 
 /* One lattice.  Potts: H = -J sum_<ij> (delta(S_i,S_j) - 1) (Sec. 2, Eq. 1);
@@ -95,6 +96,16 @@ typedef struct {
     int64_t corr_hist[2][32];
     double g_quarter, g_half;
     double mean_g_quarter, mean_g_half, corr_ratio;
+    /* |M| / N = sqrt(m2) of the current state. */
+    double absm;
+    /* Order-independent fingerprints, computed on the device:
+     * hash_spins  = sum_i mix64((i << 8) | s_i) mod 2^64 of the current state;
+     * hash_labels = sum_i mix64((i << 32) | l_i) mod 2^64 of the canonical
+     *               labels l_i of the last sweep run with SW_VERIFY (0 if none);
+     * mix64 is the SplitMix64 output function (Steele, Lea & Flood 2014).
+     * Equal states (labels) give equal hashes; the hashes let a long chain be
+     * compared with the oracle sweep by sweep without whole-state copies. */
+    uint64_t hash_spins, hash_labels;
 } sw_obs;
 
 typedef struct sw_ctx sw_ctx;
@@ -113,13 +124,27 @@ size_t sw_state_bytes(const sw_lattice* p);
 int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_ctx** out);
 
 /* Run nsweeps >= 0 sweeps (Sec. 2 steps (1)-(3), Sec. 3 for the GPU), enqueued
- * asynchronously on the stream.  flags: SW_MEASURE | SW_VERIFY | SW_PROFILE.
- * With SW_MEASURE the call synchronises every 1024 sweeps and at its end to
- * fold the per-sweep counts into the running averages. */
+ * asynchronously on the stream.  flags: SW_MEASURE | SW_VERIFY | SW_PROFILE |
+ * SW_HASH.  With SW_MEASURE (SW_HASH) the call synchronises every 1024 sweeps
+ * and at its end to fold the per-sweep counts into the running averages (to
+ * move the hashes to the host).  A kernel that finds the label forest broken
+ * (a walk longer than its node count) records it on the device; the next
+ * synchronising call then returns SW_EDEVICE and the context becomes sticky. */
 int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags);
 
 /* Observables of the current state plus the running averages (synchronises). */
 int sw_measure(sw_ctx* c, sw_obs* out);
+
+/* Per-sweep state hashes of the sweeps run with SW_HASH since the last read,
+ * oldest first: record k is out[3k] = the sweep index t of the state after
+ * that sweep (sweeps_done), out[3k+1] = its hash_spins and out[3k+2] the
+ * hash_labels of that sweep's canonical labels (definitions at sw_obs).  The
+ * canonical labels (Sec. 2: the proper label of a cluster is its smallest
+ * site index) are read from the label forest after the sweep's border merge,
+ * so every sweep of a multi-sweep call is covered.  Moves up to cap records
+ * to out (3 * cap words) and sets *n; records not moved stay for the next
+ * read.  Synchronises. */
+int sw_read_hashes(sw_ctx* c, uint64_t* out, size_t cap, size_t* n);
 
 /* Synchronous copies to host memory.  n must equal N = L*L (SW_EINVAL otherwise).
  * sw_read_labels returns the canonical labels (smallest site index of the
@@ -198,12 +223,15 @@ size_t sw_batch_bytes(const sw_lattice* ps, int32_t n);
  * sw_batch_bytes) or NULL (library-owned).  Random start for every replica. */
 int sw_batch_init(const sw_lattice* ps, int32_t n, void* dev_mem, size_t bytes, void* stream, sw_batch** out);
 /* nsweeps sweeps of every replica; flags SW_MEASURE | SW_VERIFY | SW_PROFILE |
- * SW_NO_GRAPH (the graph is used only without SW_MEASURE and SW_PROFILE). */
+ * SW_HASH | SW_NO_GRAPH (the graph is used only without SW_MEASURE, SW_HASH
+ * and SW_PROFILE). */
 int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags);
 /* Per replica, as sw_measure / sw_read_spins / sw_read_labels (synchronous). */
 int sw_batch_measure(sw_batch* b, int32_t replica, sw_obs* out);
 int sw_batch_read_spins(sw_batch* b, int32_t replica, int8_t* host, size_t n);
 int sw_batch_read_labels(sw_batch* b, int32_t replica, int32_t* host, size_t n);
+/* As sw_read_hashes, for one replica (the sweeps run with SW_HASH). */
+int sw_batch_read_hashes(sw_batch* b, int32_t replica, uint64_t* out, size_t cap, size_t* n);
 int32_t sw_batch_size(sw_batch* b);
 int sw_batch_set_schedule(sw_batch* b, int32_t merge_tiles);
 int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles);

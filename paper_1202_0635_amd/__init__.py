@@ -14,10 +14,11 @@ import math
 import numpy as np
 
 from . import _lib
-from ._lib import SW_CLOCK, SW_MEASURE, SW_NO_GRAPH, SW_POTTS, SW_PROFILE, SW_VERIFY, SwError, SwLattice, SwObs, check
+from ._lib import (SW_CLOCK, SW_HASH, SW_MEASURE, SW_NO_GRAPH, SW_POTTS, SW_PROFILE, SW_VERIFY, SwError, SwLattice,
+                   SwObs, check)
 
 __all__ = ["Lattice", "Batch", "SwError", "critical_temperature", "cutoff_table", "state_bytes",
-           "SW_MEASURE", "SW_VERIFY", "SW_PROFILE", "SW_NO_GRAPH"]
+           "SW_MEASURE", "SW_VERIFY", "SW_PROFILE", "SW_NO_GRAPH", "SW_HASH"]
 
 MODELS = {"potts": SW_POTTS, "clock": SW_CLOCK}
 
@@ -81,10 +82,17 @@ class Lattice:
         self.N = self.L * self.L
 
     # -- sweeps ------------------------------------------------------------
-    def sweep(self, n: int = 1, measure: bool = False, verify: bool = False, profile: bool = False):
-        flags = (SW_MEASURE if measure else 0) | (SW_VERIFY if verify else 0) | (SW_PROFILE if profile else 0)
+    def sweep(self, n: int = 1, measure: bool = False, verify: bool = False, profile: bool = False,
+              hash: bool = False):
+        flags = ((SW_MEASURE if measure else 0) | (SW_VERIFY if verify else 0) | (SW_PROFILE if profile else 0)
+                 | (SW_HASH if hash else 0))
         check(_lib.lib().sw_sweep(self._ctx, int(n), flags), "sw_sweep")
         return self
+
+    def hashes(self) -> np.ndarray:
+        """Per-sweep state hashes recorded by sweeps run with hash=True since
+        the last read: rows (t, hash_spins, hash_labels), uint64."""
+        return _read_hashes(lambda out, cap, n: _lib.lib().sw_read_hashes(self._ctx, out, cap, n), "sw_read_hashes")
 
     def measure(self) -> dict:
         o = SwObs()
@@ -175,6 +183,18 @@ class Lattice:
             pass
 
 
+def _read_hashes(call, where) -> np.ndarray:
+    rows = []
+    cap = 4096
+    while True:
+        out = np.zeros(3 * cap, dtype=np.uint64)
+        n = ctypes.c_size_t()
+        check(call(out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n)), where)
+        rows.append(out[: 3 * n.value].reshape(-1, 3))
+        if n.value < cap:
+            return np.concatenate(rows) if rows else np.zeros((0, 3), dtype=np.uint64)
+
+
 def _obs_dict(o: SwObs, q: int) -> dict:
     return {
         "t": int(o.sweeps_done), "samples": int(o.samples),
@@ -185,6 +205,7 @@ def _obs_dict(o: SwObs, q: int) -> dict:
         "corr_hist": np.array([o.corr_hist[0][:q], o.corr_hist[1][:q]], dtype=np.int64),
         "g_quarter": o.g_quarter, "g_half": o.g_half, "mean_g_quarter": o.mean_g_quarter,
         "mean_g_half": o.mean_g_half, "corr_ratio": o.corr_ratio,
+        "absm": o.absm, "hash_spins": int(o.hash_spins), "hash_labels": int(o.hash_labels),
     }
 
 
@@ -228,11 +249,16 @@ class Batch:
         return self.n
 
     def sweep(self, n: int = 1, measure: bool = False, verify: bool = False, profile: bool = False,
-              graph: bool = True):
+              graph: bool = True, hash: bool = False):
         flags = ((SW_MEASURE if measure else 0) | (SW_VERIFY if verify else 0) | (SW_PROFILE if profile else 0)
-                 | (0 if graph else SW_NO_GRAPH))
+                 | (0 if graph else SW_NO_GRAPH) | (SW_HASH if hash else 0))
         check(_lib.lib().sw_batch_sweep(self._b, int(n), flags), "sw_batch_sweep")
         return self
+
+    def hashes(self, r: int) -> np.ndarray:
+        """Replica r's per-sweep hashes (rows t, hash_spins, hash_labels) since the last read."""
+        return _read_hashes(lambda out, cap, n: _lib.lib().sw_batch_read_hashes(self._b, int(r), out, cap, n),
+                            "sw_batch_read_hashes")
 
     def measure(self, r: int) -> dict:
         o = SwObs()

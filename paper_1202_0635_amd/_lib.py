@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_PKG, "libswmc.so")
 
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_ESTATE, SW_EBUDGET, SW_EBUSY = 0, -1, -2, -3, -4, -5, -6
 SW_POTTS, SW_CLOCK = 0, 1
-SW_MEASURE, SW_VERIFY, SW_PROFILE, SW_NO_GRAPH = 1, 2, 4, 8
+SW_MEASURE, SW_VERIFY, SW_PROFILE, SW_NO_GRAPH, SW_HASH = 1, 2, 4, 8, 16
 
 
 class SwLattice(ctypes.Structure):
@@ -42,6 +42,9 @@ class SwObs(ctypes.Structure):
         ("mean_g_quarter", ctypes.c_double),
         ("mean_g_half", ctypes.c_double),
         ("corr_ratio", ctypes.c_double),
+        ("absm", ctypes.c_double),
+        ("hash_spins", ctypes.c_uint64),
+        ("hash_labels", ctypes.c_uint64),
     ]
 
 
@@ -77,6 +80,8 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_void_p)]),
     "sw_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
     "sw_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwObs)]),
+    "sw_read_hashes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.POINTER(ctypes.c_size_t)]),
     "sw_read_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "sw_read_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "sw_read_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
@@ -99,6 +104,8 @@ SIGNATURES = {
     "sw_batch_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SwObs)]),
     "sw_batch_read_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]),
     "sw_batch_read_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]),
+    "sw_batch_read_hashes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.POINTER(ctypes.c_size_t)]),
     "sw_batch_size": (ctypes.c_int32, [ctypes.c_void_p]),
     "sw_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),

@@ -24,7 +24,8 @@ namespace {
 constexpr int kSchedules[] = {1, 2, 4};  // first-level merge block sizes the tuner tries
 
 constexpr BatchKernel kListKernel[kNumLists] = {kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge,
-                                                kBKFlatten,   kBKFlip,      kBKCounts,     kBKCountSum};
+                                                kBKFlatten,   kBKFlip,      kBKCounts,     kBKCountSum,
+                                                kBKHash,      kBKHashSum};
 
 struct Replica {
     sw_lattice p{};
@@ -34,6 +35,7 @@ struct Replica {
     std::vector<uint32_t> table;
     Sums sums;  // running sums over measured sweeps
     bool have_canon = false;
+    std::vector<HashRecord> hashes;  // per-sweep hashes (SW_HASH) not yet read
 };
 
 }  // namespace
@@ -67,7 +69,8 @@ namespace {
 
 const char* const kListNames[kNumLists] = {"kb_bond_local<potts>", "kb_bond_local<clock>", "kb_block_merge",
                                            "kb_border_merge",      "kb_flatten",           "kb_flip",
-                                           "kb_counts",            "kb_count_sum"};
+                                           "kb_counts",            "kb_count_sum",         "kb_hash",
+                                           "kb_hash_sum"};
 
 int bfail(sw_batch* b, hipError_t e, const char* what) {
     if (b) b->sticky = true;
@@ -205,10 +208,37 @@ int launch_list(sw_batch* b, int l, bool profile, uint32_t row = 0, bool verify 
     return SW_OK;
 }
 
-int enqueue_sweep(sw_batch* b, bool profile, bool verify) {
+// One sweep of every replica; hash_row >= 0 adds the state hashes of the
+// sweep (after the border merge, before the flatten) into that ring row.
+int enqueue_sweep(sw_batch* b, bool profile, bool verify, int hash_row = -1) {
     for (int l : {kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip}) {
+        if (l == kLFlatten && hash_row >= 0) {
+            int st = launch_list(b, kLHash, profile);
+            if (!st) st = launch_list(b, kLHashSum, profile, static_cast<uint32_t>(hash_row));
+            if (st) return st;
+        }
         const int st = launch_list(b, l, profile, 0, verify);
         if (st) return st;
+    }
+    return SW_OK;
+}
+
+// Move hash ring rows [0, rows) of every replica to the host.
+int flush_hashes(sw_batch* b, int rows) {
+    if (rows <= 0) return SW_OK;
+    SWB_HIP(b, hipStreamSynchronize(b->stream));
+    std::vector<uint64_t> buf(2 * static_cast<size_t>(rows));
+    for (auto& rp : b->reps) {
+        Control ctl;
+        SWB_HIP(b, hipMemcpy(&ctl, b->base + rp.offset + rp.lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+        const int st = fault_status(ctl.fault);
+        if (st) {
+            b->sticky = true;
+            return st;
+        }
+        SWB_HIP(b, hipMemcpy(buf.data(), b->base + rp.offset + rp.lay.hash_ring, buf.size() * 8, hipMemcpyDeviceToHost));
+        for (int r = 0; r < rows; ++r)
+            rp.hashes.push_back({ctl.t - static_cast<uint64_t>(rows - 1 - r), buf[2 * r], buf[2 * r + 1]});
     }
     return SW_OK;
 }
@@ -357,11 +387,13 @@ int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags) {
     int st = check_batch(b);
     if (st) return st;
     if (nsweeps < 0) return fail(SW_EINVAL, "nsweeps must be >= 0");
-    if (flags & ~(SW_MEASURE | SW_VERIFY | SW_PROFILE | SW_NO_GRAPH)) return fail(SW_EINVAL, "unknown flag bits");
+    if (flags & ~(SW_MEASURE | SW_VERIFY | SW_PROFILE | SW_NO_GRAPH | SW_HASH))
+        return fail(SW_EINVAL, "unknown flag bits");
     const bool measure = flags & SW_MEASURE;
     const bool profile = flags & SW_PROFILE;
     const bool verify = flags & SW_VERIFY;
-    if (!measure && !profile && !(flags & SW_NO_GRAPH)) {
+    const bool hash = flags & SW_HASH;
+    if (!measure && !profile && !hash && !(flags & SW_NO_GRAPH)) {
         // replay the captured sweep; a verify sweep (the last one) runs uncaptured
         const int32_t plain = verify ? nsweeps - 1 : nsweeps;
         if (plain > 0) {
@@ -376,11 +408,16 @@ int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags) {
         }
         return SW_OK;
     }
-    int rows = 0;
+    int rows = 0, hrows = 0;
     for (int32_t s = 0; s < nsweeps; ++s) {
         const bool v = verify && (s == nsweeps - 1);
-        st = enqueue_sweep(b, profile, v);
+        st = enqueue_sweep(b, profile, v, hash ? hrows : -1);
         if (st) return st;
+        if (hash && ++hrows == kRing) {
+            st = flush_hashes(b, hrows);
+            if (st) return st;
+            hrows = 0;
+        }
         if (v)
             for (auto& rp : b->reps) rp.have_canon = true;
         if (measure) {
@@ -395,7 +432,25 @@ int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags) {
             }
         }
     }
+    st = flush_hashes(b, hrows);
+    if (st) return st;
     return flush_rings(b, rows);
+}
+
+int sw_batch_read_hashes(sw_batch* b, int32_t replica, uint64_t* out, size_t cap, size_t* n) {
+    int st = check_replica(b, replica);
+    if (st) return st;
+    if (!n || (cap > 0 && !out)) return fail(SW_EINVAL, "bad output arrays");
+    Replica& rp = b->reps[static_cast<size_t>(replica)];
+    const size_t k = rp.hashes.size() < cap ? rp.hashes.size() : cap;
+    for (size_t r = 0; r < k; ++r) {
+        out[3 * r] = rp.hashes[r].t;
+        out[3 * r + 1] = rp.hashes[r].hs;
+        out[3 * r + 2] = rp.hashes[r].hl;
+    }
+    rp.hashes.erase(rp.hashes.begin(), rp.hashes.begin() + static_cast<std::ptrdiff_t>(k));
+    *n = k;
+    return SW_OK;
 }
 
 int sw_batch_measure(sw_batch* b, int32_t replica, sw_obs* out) {
@@ -406,12 +461,24 @@ int sw_batch_measure(sw_batch* b, int32_t replica, sw_obs* out) {
     SweepArgs a = rp.args;
     a.count_row = reinterpret_cast<int64_t*>(b->base + rp.offset + rp.lay.scratch_row);
     SWB_HIP(b, launch_counts(a, b->stream));
+    const uint32_t N = static_cast<uint32_t>(rp.p.L) * static_cast<uint32_t>(rp.p.L);
+    SWB_HIP(b, launch_hash_state(a.spins, rp.have_canon ? a.canon : nullptr, N, a.hash_partial, b->stream));
     int64_t row[kRowWords];
+    uint64_t h[2];
     Control ctl;
     SWB_HIP(b, hipStreamSynchronize(b->stream));
-    SWB_HIP(b, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
     SWB_HIP(b, hipMemcpy(&ctl, b->base + rp.offset + rp.lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    st = fault_status(ctl.fault);
+    if (st) {
+        b->sticky = true;
+        return st;
+    }
+    SWB_HIP(b, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
+    SWB_HIP(b, hipMemcpy(h, a.hash_partial + 2 * static_cast<size_t>(hash_state_blocks(N)), sizeof h,
+                         hipMemcpyDeviceToHost));
     fill_obs(rp.p, row, ctl.t, rp.sums, out);
+    out->hash_spins = h[0];
+    out->hash_labels = rp.have_canon ? h[1] : 0u;
     return SW_OK;
 }
 

@@ -14,6 +14,7 @@ namespace host {
 
 // Record a status with a formatted reason (thread-local, read by sw_last_error).
 int fail(int status, const char* fmt, ...);
+const char* last_error_text();
 bool lattice_ok(const sw_lattice* p, std::string* why);
 
 double turn_cos(int n, int q);
@@ -25,8 +26,8 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v);
 
 struct Layout {
-    size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, border_roots, border_bonds, ring, scratch_row, table,
-        spins2, labels2, total;
+    size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, border_roots, border_bonds, ring, scratch_row,
+        hash_ring, hash_partial, table, spins2, labels2, total;
 };
 // Arena layout; with_pair adds the second spin and label buffers that the
 // fused flip-and-bond kernel alternates with (single-lattice contexts).
@@ -55,10 +56,22 @@ void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, const Sums& s
 SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay);
 // Control block of a fresh lattice: t = 0, no sweep target.
 extern const Control kFreshControl;
+// A control block's fault bits (set by a kernel whose forest walk exceeded its
+// step bound): SW_OK if none, else SW_EDEVICE with the reason recorded.
+const char* fault_text(uint32_t bits);
+int fault_status(uint32_t bits);
+
+// One record of a per-sweep hash stream: the sweep index of the state after
+// the sweep, H_s of that state and H_l of its canonical labels.
+struct HashRecord {
+    uint64_t t, hs, hl;
+};
 
 // Launch lists of the batched kernels: one launch per list and sweep covers
 // the workgroups of every lattice in a set.
-enum ListId { kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip, kLCounts, kLCountSum, kNumLists };
+enum ListId {
+    kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip, kLCounts, kLCountSum, kLHash, kLHashSum, kNumLists
+};
 // Workgroups list l needs for one lattice.
 uint32_t blocks_for(int l, const SweepArgs& a);
 

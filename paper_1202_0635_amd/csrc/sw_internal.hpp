@@ -40,6 +40,14 @@ constexpr uint32_t kRootFlag = 0x80000000u;
 
 constexpr int kRing = 1024;      // per-sweep count rows kept on the device
 
+// Step bounds of the forest walks.  Every link points to a smaller index, so
+// a correct forest ends every walk in fewer steps than it has nodes; a walk
+// that takes more has met a broken forest, records a fault bit in the
+// control block and stops, so a kernel never loops on it.
+constexpr uint32_t kLdsWalkCap = kTileW * kTileH;       // a tile forest in LDS (4096 nodes)
+constexpr uint32_t kGlobalWalkCap = 1u << 22;           // the global forest
+enum FaultBits : uint32_t { kFaultLds = 1u, kFaultGlobal = 2u, kFaultFlip = 4u, kFaultHash = 8u };
+
 // Per-tile border record written by the bond kernel.  Edge e of border_roots:
 // 0 right column, 1 bottom row, 2 left column, 3 top row (the last valid
 // column / row of a ragged tile).  Masks: bit = row (columns) or column (rows).
@@ -64,7 +72,9 @@ struct Control {
     uint32_t mirror;  // clock model: mirror index of the sweep in progress
     uint32_t live;    // the sweep in progress runs (t < target when it started)
     uint32_t changed; // label-equivalence labelers: a scan found a smaller label
-    uint32_t pad[9];
+    uint32_t fault;   // nonzero: a forest walk exceeded its step bound (kFault* bits); the
+                      // kernel that saw it gave up its walks, the host reports SW_EDEVICE
+    uint32_t pad[8];
 };
 static_assert(sizeof(Control) == 64, "control block is one 64-byte line");
 
@@ -83,6 +93,8 @@ struct SweepArgs {
     uint32_t* count_partial;  // [count_blocks(L)][kRowWords]: each count workgroup's bins
     uint32_t* border_roots;   // [tiles][4][64]: tile-local root (site index) of each edge site
     uint64_t* border_bonds;   // [tiles][kBorderMasks]: the bond bits the border joins read
+    uint64_t* hash_ring;      // [kRing][2]: per-sweep state hashes (spins, canonical labels)
+    uint64_t* hash_partial;   // [hash_blocks(L)][2]: each hash workgroup's sums
     int L, q, model, w64;
     int tiles_x, tiles_y;
     int tile_waves;       // waves per bond-kernel workgroup: kWaves or kWavesSmall (single
@@ -105,6 +117,24 @@ hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flip(const SweepArgs& a, bool verify, hipStream_t s);
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s);
+// Per-sweep state hashes, run after the border merge of a sweep (before the
+// flatten): the new state (the flip this sweep decides) and its canonical
+// labels, summed into hash_ring[row] (which must hold zeros).
+hipError_t launch_hash_sweep(const SweepArgs& a, uint32_t row, hipStream_t s);
+// Hashes of given arrays: spins[n] and, if canon is not null, canon[n].
+// part_and_out holds kHashPartWords words: the partial sums of up to 1024
+// workgroups, then the two results (at 2 * blocks, 2 * blocks + 1 with
+// blocks = hash_state_blocks(n)).
+hipError_t launch_hash_state(const int8_t* spins, const uint32_t* canon, uint32_t n, uint64_t* out, hipStream_t s);
+constexpr size_t kHashPartWords = 2 * 1024 + 2;
+__host__ __device__ inline uint32_t hash_state_blocks(uint64_t n) {
+    const uint64_t want = (n + 1023) / 1024;
+    return want == 0 ? 1u : (want < 1024 ? static_cast<uint32_t>(want) : 1024u);
+}
+__host__ __device__ inline uint32_t hash_blocks(int L) {
+    const uint64_t n = (static_cast<uint64_t>(L) * L + 1023) / 1024;
+    return static_cast<uint32_t>(n < 1024 ? n : 1024);
+}
 // The paper's labelers (Sec. 3) as an ablation: bonds only, then label
 // equivalence iterations, then root words at the sites that label themselves.
 enum Labeler { kUnionFind = 0, kHawick = 1, kKalentev = 2 };
@@ -126,7 +156,7 @@ __host__ __device__ inline uint32_t merge_blocks_x(int tiles_x, int mt) {
 // Batched launches: one launch covers the workgroups of every replica.
 enum BatchKernel {
     kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge, kBKFlatten, kBKFlip, kBKFlipVerify, kBKCounts,
-    kBKCountSum, kNumBatchKernels
+    kBKCountSum, kBKHash, kBKHashSum, kNumBatchKernels
 };
 struct BatchLaunch {
     const SweepArgs* reps;  // device replica table
@@ -138,7 +168,7 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
 
 enum KernelId {
     kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kKFlipBond,
-    kKBondsOnly, kKLeIteration, kKLeRoots, kNumKernels
+    kKBondsOnly, kKLeIteration, kKLeRoots, kKHash, kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];
 

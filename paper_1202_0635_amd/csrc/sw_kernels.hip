@@ -30,7 +30,7 @@ namespace swmc {
 
 const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge",   "k_border_merge", "k_flatten",
                                                "k_flip",       "k_counts",        "k_flip_bond",    "k_bonds_only",
-                                               "k_le_iteration", "k_le_roots"};
+                                               "k_le_iteration", "k_le_roots",    "k_hash"};
 
 namespace {
 
@@ -42,13 +42,24 @@ __device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// A walk that has taken more steps than its forest has nodes has met a broken
+// forest (links must point to smaller indices): it records a fault bit in the
+// control block and stops, so a kernel ends instead of looping.
+__device__ __noinline__ void record_fault(Control* ctl, uint32_t bit) {
+    __hip_atomic_fetch_or(&ctl->fault, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Root of x in the tile forest (parents always have smaller indices), with
 // path halving: a visited node is pointed at its grandparent.  A halving store
 // may overwrite a concurrent lowering of that node; the union that lowered it
 // continues with the node's previous parent, so no connection is lost.
 // p is P[x], already loaded by the caller.
-__device__ __forceinline__ uint32_t lds_find_from(uint32_t* P, uint32_t x, uint32_t p) {
-    while (p != x) {
+__device__ __forceinline__ uint32_t lds_find_from(uint32_t* P, uint32_t x, uint32_t p, Control* ctl) {
+    for (uint32_t n = 0; p != x; ++n) {
+        if (n >= kLdsWalkCap) {
+            record_fault(ctl, kFaultLds);
+            return x;
+        }
         const uint32_t gp = lds_load(&P[p]);
         if (gp == p) return p;
         lds_store(&P[x], gp);
@@ -58,15 +69,22 @@ __device__ __forceinline__ uint32_t lds_find_from(uint32_t* P, uint32_t x, uint3
     return x;
 }
 
-__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x) { return lds_find_from(P, x, lds_load(&P[x])); }
+__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, Control* ctl) {
+    return lds_find_from(P, x, lds_load(&P[x]), ctl);
+}
 
 // Join the sets of a and b: the larger root is lowered to the smaller with an
 // LDS atomic min; if that root had meanwhile been linked elsewhere, its old
-// parent still has to be joined, so the loop continues with it.
-__device__ __forceinline__ void lds_union(uint32_t* P, uint32_t a, uint32_t b) {
-    while (true) {
-        a = lds_find(P, a);
-        b = lds_find(P, b);
+// parent still has to be joined, so the loop continues with it (each round
+// lowers a root, so a correct forest ends it within its node count).
+__device__ __forceinline__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, Control* ctl) {
+    for (uint32_t n = 0;; ++n) {
+        if (n >= kLdsWalkCap) {
+            record_fault(ctl, kFaultLds);
+            return;
+        }
+        a = lds_find(P, a, ctl);
+        b = lds_find(P, b, ctl);
         if (a == b) return;
         if (a < b) {
             const uint32_t tmp = a;
@@ -92,8 +110,13 @@ __device__ __forceinline__ void g_store(uint32_t* p, uint32_t v) {
 // is pointed at its grandparent.  Only non-root words are rewritten and only
 // with an ancestor's index, so a concurrent compare-and-swap (which targets
 // root words) is never disturbed.
-__device__ __forceinline__ uint32_t g_find_from(uint32_t* lab, uint32_t x, uint32_t w, uint32_t* word) {
-    while (!(w & kRootFlag)) {
+__device__ __forceinline__ uint32_t g_find_from(uint32_t* lab, uint32_t x, uint32_t w, uint32_t* word,
+                                                Control* ctl) {
+    for (uint32_t n = 0; !(w & kRootFlag); ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(ctl, kFaultGlobal);
+            break;
+        }
         const uint32_t w2 = g_load(&lab[w]);
         if (w2 & kRootFlag) {
             *word = w2;
@@ -113,8 +136,13 @@ __device__ __forceinline__ uint32_t g_find_from(uint32_t* lab, uint32_t x, uint3
 // the following compare-and-swap fail.  A word read as a non-root can no
 // longer be a root, so the halving stores never touch the root words the
 // compare-and-swap works on.
-__device__ __forceinline__ uint32_t c_find_from(uint32_t* lab, uint32_t x, uint32_t w, uint32_t* word) {
-    while (!(w & kRootFlag)) {
+__device__ __forceinline__ uint32_t c_find_from(uint32_t* lab, uint32_t x, uint32_t w, uint32_t* word,
+                                                Control* ctl) {
+    for (uint32_t n = 0; !(w & kRootFlag); ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(ctl, kFaultGlobal);
+            break;
+        }
         const uint32_t w2 = lab[w];
         if (w2 & kRootFlag) {
             *word = w2;
@@ -132,8 +160,12 @@ __device__ __forceinline__ uint32_t c_find_from(uint32_t* lab, uint32_t x, uint3
 // with root words wa and wb: the larger root is linked under the smaller one
 // by compare-and-swap on its root word; after a failed swap the walk uses
 // coherent loads (and halves the paths it visits).
-__device__ void g_union_roots(uint32_t* lab, uint32_t a, uint32_t wa, uint32_t b, uint32_t wb) {
-    while (a != b) {
+__device__ void g_union_roots(uint32_t* lab, uint32_t a, uint32_t wa, uint32_t b, uint32_t wb, Control* ctl) {
+    for (uint32_t n = 0; a != b; ++n) {
+        if (n >= kGlobalWalkCap || !(wa & wb & kRootFlag)) {  // a walk gave up: the forest is broken
+            record_fault(ctl, kFaultGlobal);
+            return;
+        }
         if (a > b) {
             uint32_t tmp = a;
             a = b;
@@ -149,8 +181,8 @@ __device__ void g_union_roots(uint32_t* lab, uint32_t a, uint32_t wa, uint32_t b
         // the failed swap returned b's current word; a's first load is
         // issued before b's walk goes on
         const uint32_t wa0 = g_load(&lab[a]);
-        b = g_find_from(lab, b, expected, &wb);
-        a = g_find_from(lab, a, wa0, &wa);
+        b = g_find_from(lab, b, expected, &wb, ctl);
+        a = g_find_from(lab, a, wa0, &wa, ctl);
     }
 }
 
@@ -230,9 +262,15 @@ __device__ __forceinline__ int flipped(uint32_t root_word, int old, int m, int q
     return v;
 }
 
-__device__ __forceinline__ uint32_t root_word_of(const uint32_t* lab, uint32_t i) {
+__device__ __forceinline__ uint32_t root_word_of(const uint32_t* lab, uint32_t i, Control* ctl) {
     uint32_t w = lab[i];
-    while (!(w & kRootFlag)) w = lab[w];
+    for (uint32_t n = 0; !(w & kRootFlag); ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(ctl, kFaultFlip);
+            break;
+        }
+        w = lab[w];
+    }
     return w;
 }
 
@@ -437,7 +475,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         // (the fused kernel's spin buffer is being written by other
         // workgroups, so its spins are recomputed from the previous forest)
         auto spin_at = [&](uint32_t j) -> int {
-            if (kFused) return flipped<kClock>(root_word_of(a.labels_prev, j), kClock ? a.spins_prev[j] : 0, m_prev, q);
+            if (kFused) return flipped<kClock>(root_word_of(a.labels_prev, j, a.ctl), kClock ? a.spins_prev[j] : 0, m_prev, q);
             return a.spins[j];
         };
         const int s = kClock ? spin_at(i) : 0;  // a Potts tie implies equal spins
@@ -506,14 +544,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             const int ly = ly_base + r;
             const uint64_t starts = ~((uniform64(raw_r[ly]) & in_tile_r) << 1);  // first sites of the runs
             const int start = 63 - __clzll(starts & le_lane);
-            const bool run_start = __builtin_amdgcn_inverse_ballot_w64(starts);
             const uint32_t node = static_cast<uint32_t>(ly * kTileW + start);
             // the label above is usually still a root: one load, and the
             // find loop runs only where it is not
             uint32_t cand = kNone;
             if (r > 0 && (kFull || y0 + ly < L) && __builtin_amdgcn_inverse_ballot_w64(d_above)) {
                 const uint32_t p = lds_load(&P[lab_prev]);
-                cand = (p == lab_prev) ? p : lds_find_from(P, lab_prev, p);
+                cand = (p == lab_prev) ? p : lds_find_from(P, lab_prev, p, a.ctl);
             }
             // every site points at its run's first site; the first site's
             // entry then takes the smallest root above the run (roots of
@@ -527,7 +564,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             // lab at once, and join its new parent too if it was linked meanwhile
             if (cand != kNone && cand != lab) {
                 const uint32_t old = __hip_atomic_fetch_min(&P[cand], lab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (old != cand) lds_union(P, old, lab);
+                if (old != cand) lds_union(P, old, lab, a.ctl);
             }
             lab_prev = lab;
             d_above = uniform64(raw_d[ly]);
@@ -547,7 +584,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         if (((d >> lane) & 1ull) &&
             !(lane > 0 && ((d >> (lane - 1)) & 1ull) && ((raw_r[ly] >> (lane - 1)) & 1ull) &&
               ((raw_r[ly + 1] >> (lane - 1)) & 1ull)))
-            lds_union(P, lds_load(&P[ly * kTileW + lane]), lds_load(&P[(ly + 1) * kTileW + lane]));
+            lds_union(P, lds_load(&P[ly * kTileW + lane]), lds_load(&P[(ly + 1) * kTileW + lane]), a.ctl);
     }
     __syncthreads();
 
@@ -564,11 +601,15 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             if (p != self) {
                 uint32_t x = p, gp = lds_load(&P[p]);
                 if (gp != p) {
-                    while (gp != x) {
+                    for (uint32_t n = 0; gp != x; ++n) {
+                        if (n >= kLdsWalkCap) {
+                            record_fault(a.ctl, kFaultLds);
+                            break;
+                        }
                         x = gp;
                         gp = lds_load(&P[x]);
                     }
-                    lds_store(&P[self], x);
+                    lds_store(&P[self], x & (kLdsWalkCap - 1u));
                 }
             }
         }
@@ -702,9 +743,13 @@ __device__ __forceinline__ uint32_t hash_insert(uint32_t* keys, uint32_t key) {
     return kSlots;  // unreachable: the table never fills
 }
 
-__device__ __forceinline__ uint32_t node_find(uint32_t* par, uint32_t x) {
+__device__ __forceinline__ uint32_t node_find(uint32_t* par, uint32_t x, Control* ctl) {
     uint32_t p = lds_load(&par[x]);
-    while (p != x) {
+    for (uint32_t n = 0; p != x; ++n) {
+        if (n >= kHashSlots) {
+            record_fault(ctl, kFaultLds);
+            return x;
+        }
         const uint32_t gp = lds_load(&par[p]);
         if (gp == p) return p;
         lds_store(&par[x], gp);
@@ -716,10 +761,14 @@ __device__ __forceinline__ uint32_t node_find(uint32_t* par, uint32_t x) {
 
 // Join the sets of nodes a and b: the root with the larger key (site index)
 // is linked under the other by compare-and-swap; a lost race retries.
-__device__ __forceinline__ void node_union(uint32_t* par, const uint32_t* keys, uint32_t a, uint32_t b) {
-    while (true) {
-        a = node_find(par, a);
-        b = node_find(par, b);
+__device__ __forceinline__ void node_union(uint32_t* par, const uint32_t* keys, uint32_t a, uint32_t b, Control* ctl) {
+    for (uint32_t n = 0;; ++n) {
+        if (n >= kHashSlots) {
+            record_fault(ctl, kFaultLds);
+            return;
+        }
+        a = node_find(par, a, ctl);
+        b = node_find(par, b, ctl);
         if (a == b) return;
         if (keys[a] > keys[b]) {
             const uint32_t tmp = a;
@@ -769,12 +818,12 @@ __device__ __forceinline__ void block_merge(const SweepArgs& a, const int bx, co
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kPer; ++r)
-        if (ends[r][0] < kHashSlots && ends[r][1] < kHashSlots) node_union(par, keys, ends[r][0], ends[r][1]);
+        if (ends[r][0] < kHashSlots && ends[r][1] < kHashSlots) node_union(par, keys, ends[r][0], ends[r][1], a.ctl);
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < kHashSlots; k += blockDim.x) {
         const uint32_t key = keys[k];
         if (key == kEmptyKey) continue;
-        const uint32_t r = node_find(par, k);
+        const uint32_t r = node_find(par, k, a.ctl);
         if (r != k) a.labels[key] = keys[r];
     }
 }
@@ -810,8 +859,8 @@ __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t 
     if (b.active) {
         // the two first loads are issued together; most walks end there
         const uint32_t wi = a.labels[b.i], wj = a.labels[b.j];
-        ra = c_find_from(a.labels, b.i, wi, &wa);
-        rb = c_find_from(a.labels, b.j, wj, &wb);
+        ra = c_find_from(a.labels, b.i, wi, &wa, a.ctl);
+        rb = c_find_from(a.labels, b.j, wj, &wb, a.ctl);
         if (ra > rb) {
             uint32_t tmp = ra;
             ra = rb;
@@ -821,19 +870,23 @@ __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t 
             wb = tmp;
         }
     }
-    if (wave_first(b.active && ra != rb, ra, rb)) g_union_roots(a.labels, ra, wa, rb, wb);
+    if (wave_first(b.active && ra != rb, ra, rb)) g_union_roots(a.labels, ra, wa, rb, wb, a.ctl);
 }
 
 // After the merge: every tile-local root at the end of a border bond that
 // has been linked is pointed straight at its cluster root, so that any site
 // reaches the root word in at most two loads (site -> tile-local root ->
 // root).  The walk halves the path on the way.
-__device__ __forceinline__ void flatten_root(uint32_t* lab, uint32_t r) {
+__device__ __forceinline__ void flatten_root(uint32_t* lab, uint32_t r, Control* ctl) {
     const uint32_t w = lab[r];
     if (w & kRootFlag) return;  // still a cluster root
     uint32_t x = w;
     uint32_t wx = lab[x];
-    while (!(wx & kRootFlag)) {
+    for (uint32_t n = 0; !(wx & kRootFlag); ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(ctl, kFaultGlobal);
+            return;
+        }
         const uint32_t w2 = lab[wx];
         if (w2 & kRootFlag) {
             x = wx;
@@ -852,10 +905,15 @@ __device__ __forceinline__ void flatten_root(uint32_t* lab, uint32_t r) {
 // written: a halving store could overwrite a copy another thread had just
 // stored.  Every linked node is the end of some border bond, so every one of
 // them is visited.
-__device__ __forceinline__ void copy_root_word(uint32_t* lab, uint32_t r, uint32_t w) {
+__device__ __forceinline__ void copy_root_word(uint32_t* lab, uint32_t r, uint32_t w, Control* ctl) {
     if (w & kRootFlag) return;  // a cluster root, or a copy already
-    do w = lab[w];
-    while (!(w & kRootFlag));
+    for (uint32_t n = 0; !(w & kRootFlag); ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(ctl, kFaultGlobal);
+            return;
+        }
+        w = lab[w];
+    }
     lab[r] = w;
 }
 
@@ -876,11 +934,11 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
         // both first loads are issued together (a lane without a walk reads
         // site 0 and discards it)
         const uint32_t wi = a.labels[do_i ? i : 0u], wj = a.labels[do_j ? j : 0u];
-        if (do_i) copy_root_word(a.labels, i, wi);
-        if (do_j) copy_root_word(a.labels, j, wj);
+        if (do_i) copy_root_word(a.labels, i, wi, a.ctl);
+        if (do_j) copy_root_word(a.labels, j, wj, a.ctl);
     } else {
-        if (do_i) flatten_root(a.labels, i);
-        if (do_j) flatten_root(a.labels, j);
+        if (do_i) flatten_root(a.labels, i, a.ctl);
+        if (do_j) flatten_root(a.labels, j, a.ctl);
     }
 }
 
@@ -947,7 +1005,11 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
     }
     // Further steps (paths through merged roots), sixteen paths together.
     bool pending = true;
-    while (pending) {
+    for (uint32_t n = 0; pending; ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(a.ctl, kFaultFlip);
+            break;
+        }
         pending = false;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1273,6 +1335,127 @@ __device__ __forceinline__ void count_sum(const SweepArgs& a, int64_t* row) {
 }
 
 // ---------------------------------------------------------------------------
+// State hashes for checking long chains without dumping whole states:
+// H_s = sum_i mix64((i << 8) | s_i) and H_l = sum_i mix64((i << 32) | l_i)
+// mod 2^64, l_i the canonical label (smallest site index of i's cluster),
+// with the SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014).
+// Sums do not depend on the order of the sites, so any grid may compute them.
+// Each workgroup writes its partial sums; one workgroup adds them.
+// ---------------------------------------------------------------------------
+constexpr int kHashThreads = 256;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ void hash_store_partial(uint64_t hs, uint64_t hl, uint64_t* part) {
+    __shared__ uint64_t wsum[2][kHashThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        hs += __shfl_xor(hs, off, 64);
+        hl += __shfl_xor(hl, off, 64);
+    }
+    const int wave = static_cast<int>(threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) {
+        wsum[0][wave] = hs;
+        wsum[1][wave] = hl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint64_t v = 0;
+        for (int w = 0; w < kHashThreads / 64; ++w) v += wsum[threadIdx.x][w];
+        part[threadIdx.x] = v;
+    }
+}
+
+// The sweep's new state and canonical labels, read from the forest after the
+// border merge: every site walks to its cluster root (the root word carries
+// the cluster's draw) and applies the flip the sweep decides, as k_flip does.
+__device__ __forceinline__ void hash_sweep(const SweepArgs& a, uint32_t block, uint32_t nblocks) {
+    if (!a.ctl->live) return;
+    const uint32_t N = __umul24(a.L, a.L);
+    const int m = a.model == 1 ? static_cast<int>(a.ctl->mirror) : 0;
+    uint64_t hs = 0, hl = 0;
+    bool broken = false;
+    for (uint32_t i = block * kHashThreads + threadIdx.x; i < N; i += nblocks * kHashThreads) {
+        uint32_t x = i, w = a.labels[i];
+        for (uint32_t n = 0; !(w & kRootFlag); ++n) {
+            if (n >= kGlobalWalkCap) {
+                broken = true;
+                break;
+            }
+            x = w;
+            w = a.labels[x];
+        }
+        int v;
+        if (a.model == 0) {
+            v = static_cast<int>(w & 0xFFu);
+        } else {
+            v = a.spins[i];
+            if (w & 1u) {
+                v = m - v;
+                if (v < 0) v += a.q;
+            }
+        }
+        hs += mix64((static_cast<uint64_t>(i) << 8) | static_cast<uint8_t>(v));
+        hl += mix64((static_cast<uint64_t>(i) << 32) | x);
+    }
+    if (broken) record_fault(a.ctl, kFaultHash);
+    hash_store_partial(hs, hl, a.hash_partial + 2 * static_cast<size_t>(block));
+}
+
+// Sum of the partial sums of nblocks workgroups into out[0..1].
+__device__ __forceinline__ void hash_sum(const uint64_t* part, uint32_t nblocks, uint64_t* out) {
+    uint64_t hs = 0, hl = 0;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += kHashThreads) {
+        hs += part[2 * static_cast<size_t>(b)];
+        hl += part[2 * static_cast<size_t>(b) + 1];
+    }
+    uint64_t tot[2];
+    __shared__ uint64_t wsum[2][kHashThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        hs += __shfl_xor(hs, off, 64);
+        hl += __shfl_xor(hl, off, 64);
+    }
+    const int wave = static_cast<int>(threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) {
+        wsum[0][wave] = hs;
+        wsum[1][wave] = hl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        tot[threadIdx.x] = 0;
+        for (int w = 0; w < kHashThreads / 64; ++w) tot[threadIdx.x] += wsum[threadIdx.x][w];
+        out[threadIdx.x] = tot[threadIdx.x];
+    }
+}
+
+__global__ void __launch_bounds__(kHashThreads) k_hash_sweep(SweepArgs a) { hash_sweep(a, blockIdx.x, gridDim.x); }
+
+__global__ void __launch_bounds__(kHashThreads) k_hash_sum(SweepArgs a, uint32_t row) {
+    if (!a.ctl->live) return;
+    hash_sum(a.hash_partial, hash_blocks(a.L), a.hash_ring + 2 * static_cast<size_t>(row));
+}
+
+// Hashes of given arrays (H_l only when canon is given; 0 otherwise).
+__global__ void __launch_bounds__(kHashThreads) k_hash_state(const int8_t* spins, const uint32_t* canon, uint32_t n,
+                                                             uint64_t* part) {
+    uint64_t hs = 0, hl = 0;
+    for (uint32_t i = blockIdx.x * kHashThreads + threadIdx.x; i < n; i += gridDim.x * kHashThreads) {
+        hs += mix64((static_cast<uint64_t>(i) << 8) | static_cast<uint8_t>(spins[i]));
+        if (canon) hl += mix64((static_cast<uint64_t>(i) << 32) | canon[i]);
+    }
+    hash_store_partial(hs, hl, part + 2 * static_cast<size_t>(blockIdx.x));
+}
+
+__global__ void __launch_bounds__(kHashThreads) k_hash_state_sum(const uint64_t* part, uint32_t nblocks, uint64_t* out) {
+    hash_sum(part, nblocks, out);
+}
+
+// ---------------------------------------------------------------------------
 // Entry points.  k_*: one lattice per launch.  kb_*: one launch covers every
 // replica of a batch; workgroup b serves replica map[b], local block
 // b - begin[replica].
@@ -1413,7 +1596,13 @@ __global__ void __launch_bounds__(256) k_le_analysis_r(SweepArgs a, uint32_t* R)
     const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
     if (a.labels[i] != i) return;
     uint32_t ref = R[i];
-    while (ref != R[ref]) ref = R[ref];
+    for (uint32_t n = 0; ref != R[ref]; ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(a.ctl, kFaultGlobal);
+            return;
+        }
+        ref = R[ref];
+    }
     R[i] = ref;
 }
 
@@ -1431,7 +1620,13 @@ __global__ void __launch_bounds__(256) k_le_analysis(SweepArgs a) {
     const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
     uint32_t l = a.labels[i];
     if (a.labels[l] == l) return;
-    while (l != a.labels[l]) l = a.labels[l];
+    for (uint32_t n = 0; l != a.labels[l]; ++n) {
+        if (n >= kGlobalWalkCap) {
+            record_fault(a.ctl, kFaultGlobal);
+            return;
+        }
+        l = a.labels[l];
+    }
     a.labels[i] = l;
 }
 
@@ -1505,6 +1700,19 @@ __global__ void __launch_bounds__(kCountSumThreads) kb_count_sum(BatchMap m, uin
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
     count_sum(a, a.count_row + static_cast<size_t>(row) * kRowWords);
+}
+
+__global__ void __launch_bounds__(kHashThreads) kb_hash(BatchMap m) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    hash_sweep(a, local, hash_blocks(a.L));
+}
+
+__global__ void __launch_bounds__(kHashThreads) kb_hash_sum(BatchMap m, uint32_t row) {
+    uint32_t local;
+    const SweepArgs& a = m.reps[batch_replica(m, &local)];
+    if (!a.ctl->live) return;
+    hash_sum(a.hash_partial, hash_blocks(a.L), a.hash_ring + 2 * static_cast<size_t>(row));
 }
 
 }  // namespace
@@ -1613,6 +1821,22 @@ hipError_t launch_le_roots(const SweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_hash_sweep(const SweepArgs& a, uint32_t row, hipStream_t s) {
+    hipLaunchKernelGGL(k_hash_sweep, dim3(hash_blocks(a.L)), dim3(kHashThreads), 0, s, a);
+    hipLaunchKernelGGL(k_hash_sum, dim3(1), dim3(kHashThreads), 0, s, a, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_state(const int8_t* spins, const uint32_t* canon, uint32_t n, uint64_t* part_and_out,
+                             hipStream_t s) {
+    // part_and_out: [blocks][2] partial sums, then the two results
+    const uint32_t nb = hash_state_blocks(n);
+    hipLaunchKernelGGL(k_hash_state, dim3(nb), dim3(kHashThreads), 0, s, spins, canon, n, part_and_out);
+    hipLaunchKernelGGL(k_hash_state_sum, dim3(1), dim3(kHashThreads), 0, s, static_cast<const uint64_t*>(part_and_out),
+                       nb, part_and_out + 2 * static_cast<size_t>(nb));
+    return hipGetLastError();
+}
+
 hipError_t launch_counts(const SweepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_counts, dim3(count_blocks(a.L)), dim3(kCountThreads), count_lds_bytes(a.q, a.model), s, a);
     hipLaunchKernelGGL(k_count_sum, dim3(1), dim3(kCountSumThreads), 0, s, a);
@@ -1637,6 +1861,8 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
         case kBKFlipVerify: hipLaunchKernelGGL(kb_flip<true>, grid, dim3(256), 0, s, m); break;
         case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(kCountThreads), count_lds_bytes(3, 1), s, m); break;
         case kBKCountSum: hipLaunchKernelGGL(kb_count_sum, grid, dim3(kCountSumThreads), 0, s, m, row); break;
+        case kBKHash: hipLaunchKernelGGL(kb_hash, grid, dim3(kHashThreads), 0, s, m); break;
+        case kBKHashSum: hipLaunchKernelGGL(kb_hash_sum, grid, dim3(kHashThreads), 0, s, m, row); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

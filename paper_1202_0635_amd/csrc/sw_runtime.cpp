@@ -1,5 +1,6 @@
-// Host runtime of libswmc: parameter checks, the FP64 cutoff table, the
-// device arena, kernel sequencing and the C-ABI of include/sw.h.
+// Host runtime of libswmc for single lattices: the device arena, kernel
+// sequencing and the C-ABI of include/sw.h (parameter checks, the cutoff
+// table and the arena layout are in sw_host.cpp).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -15,234 +16,6 @@
 
 using namespace swmc;
 using namespace swmc::host;
-
-namespace swmc {
-namespace host {
-
-thread_local std::string g_last_error;
-
-int fail(int status, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    std::vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return status;
-}
-
-bool lattice_ok(const sw_lattice* p, std::string* why) {
-    if (!p) return *why = "null sw_lattice", false;
-    if (p->L < 2 || p->L > 46340) return *why = "L must be in [2, 46340]", false;
-    if (p->q < 2 || p->q > 32) return *why = "q must be in [2, 32]", false;
-    if (p->model != SW_POTTS && p->model != SW_CLOCK) return *why = "model must be SW_POTTS or SW_CLOCK", false;
-    if (p->reserved != 0) return *why = "reserved must be 0", false;
-    if (!(p->T > 0.0) || !std::isfinite(p->T)) return *why = "T must be positive and finite", false;
-    if (!(p->J > 0.0) || !std::isfinite(p->J)) return *why = "J must be positive and finite", false;
-    return true;
-}
-
-// ---------------------------------------------------------------------------
-// Cutoff table (Sec. 2 step (ii); Sec. 4 embedded cluster).  A bond is active
-// iff its 32-bit uniform u < C, C = floor(2^32 p) with p = -expm1(-x) in FP64.
-// ---------------------------------------------------------------------------
-constexpr double kPi = 3.14159265358979323846;
-
-// cos / sin of the angle 2 pi n / q; angles that are multiples of 30 degrees
-// with a rational cosine (sine) are exact, the rest come from libm.
-double turn_cos(int n, int q) {
-    n = ((n % q) + q) % q;
-    if ((12 * n) % q == 0) {
-        static const double exact[12] = {1.0, NAN, 0.5, 0.0, -0.5, NAN, -1.0, NAN, -0.5, 0.0, 0.5, NAN};
-        const double v = exact[(12 * n) / q];
-        if (!std::isnan(v)) return v;
-    }
-    return std::cos(2.0 * kPi * static_cast<double>(n) / static_cast<double>(q));
-}
-
-double turn_sin(int n, int q) {
-    n = ((n % q) + q) % q;
-    if ((12 * n) % q == 0) {
-        static const double exact[12] = {0.0, 0.5, NAN, 1.0, NAN, 0.5, 0.0, -0.5, NAN, -1.0, NAN, -0.5};
-        const double v = exact[(12 * n) / q];
-        if (!std::isnan(v)) return v;
-    }
-    return std::sin(2.0 * kPi * static_cast<double>(n) / static_cast<double>(q));
-}
-
-uint32_t cutoff(double x) {
-    const double c = std::floor(std::ldexp(-std::expm1(-x), 32));
-    if (c >= 4294967295.0) return 0xFFFFFFFFu;
-    if (c <= 0.0) return 0u;
-    return static_cast<uint32_t>(c);
-}
-
-size_t table_entries(const sw_lattice& p) {
-    return p.model == SW_POTTS ? static_cast<size_t>(p.q) * p.q : static_cast<size_t>(p.q) * p.q * p.q;
-}
-
-void build_table(const sw_lattice& p, uint32_t* out) {
-    const int q = p.q;
-    if (p.model == SW_POTTS) {
-        const uint32_t c = cutoff(p.J / p.T);
-        for (int s = 0; s < q; ++s)
-            for (int u = 0; u < q; ++u) out[s * q + u] = (s == u) ? c : 0u;
-        return;
-    }
-    // Mirror m reflects state k to (m - k) mod q; the projection of two states
-    // on the mirror normal multiplies to [cos(a-b) - cos(a+b-m)] / 2 (angles in
-    // units of 2 pi / q); only positive products can bond, with x = 2 J P / T.
-    for (int m = 0; m < q; ++m)
-        for (int s = 0; s < q; ++s)
-            for (int u = 0; u < q; ++u) {
-                const double P = 0.5 * (turn_cos(s - u, q) - turn_cos(s + u - m, q));
-                out[(static_cast<size_t>(m) * q + s) * q + u] = P > 0.0 ? cutoff(2.0 * p.J * P / p.T) : 0u;
-            }
-}
-
-// ---------------------------------------------------------------------------
-// Device arena layout.
-// ---------------------------------------------------------------------------
-size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-Layout layout_of(const sw_lattice& p, bool with_pair) {
-    const size_t L = static_cast<size_t>(p.L);
-    const size_t N = L * L;
-    const size_t w64 = (L + 63) / 64;
-    Layout l{};
-    size_t o = 0;
-    l.ctl = o; o += up(sizeof(Control));
-    l.spins = o; o += up(N);
-    l.bond_r = o; o += up(L * w64 * 8);
-    l.bond_d = o; o += up(L * w64 * 8);
-    l.labels = o; o += up(N * 4);
-    l.canon = o; o += up(N * 4);
-    l.count_partial = o; o += up(static_cast<size_t>(count_blocks(p.L)) * kRowWords * 4);
-    const size_t tiles = ((L + kTileW - 1) / kTileW) * ((L + kTileH - 1) / kTileH);
-    l.border_roots = o; o += up(tiles * 4 * kTileW * 4);
-    l.border_bonds = o; o += up(tiles * kBorderMasks * 8);
-    l.ring = o; o += up(static_cast<size_t>(kRing) * kRowWords * 8);
-    l.scratch_row = o; o += up(kRowWords * 8);
-    l.table = o; o += up(table_entries(p) * 4);
-    if (with_pair) {
-        l.spins2 = o; o += up(N);
-        l.labels2 = o; o += up(N * 4);
-    }
-    l.total = o;
-    return l;
-}
-
-Observables observables_of(const sw_lattice& p, const int64_t* row) {
-    const double N = static_cast<double>(p.L) * static_cast<double>(p.L);
-    const int q = p.q;
-    const int64_t* hist = row + kRowHist;
-    const int64_t* pair = row + kRowPair;
-    Observables o;
-    if (p.model == SW_POTTS) {
-        o.e = p.J * (2.0 * N - static_cast<double>(pair[0])) / N;
-        double s2 = 0.0;
-        for (int k = 0; k < q; ++k) s2 += static_cast<double>(hist[k]) * static_cast<double>(hist[k]);
-        o.m2 = (static_cast<double>(q) * s2 - N * N) / (static_cast<double>(q - 1) * N * N);
-    } else {
-        double e = 0.0;
-        for (int d = 0; d < q; ++d) e += static_cast<double>(pair[d]) * turn_cos(d, q);
-        o.e = -p.J * e / N;
-        double mx = 0.0, my = 0.0;
-        for (int k = 0; k < q; ++k) {
-            mx += static_cast<double>(hist[k]) * turn_cos(k, q);
-            my += static_cast<double>(hist[k]) * turn_sin(k, q);
-        }
-        o.m2 = (mx * mx + my * my) / (N * N);
-        // G(r): mean over the 2N displaced pairs of cos(theta_j - theta_i)
-        double g1 = 0.0, g2 = 0.0;
-        for (int d = 0; d < q; ++d) {
-            g1 += static_cast<double>(row[kRowCorr1 + d]) * turn_cos(d, q);
-            g2 += static_cast<double>(row[kRowCorr2 + d]) * turn_cos(d, q);
-        }
-        o.g1 = g1 / (2.0 * N);
-        o.g2 = g2 / (2.0 * N);
-    }
-    return o;
-}
-
-const Control kFreshControl = {0ull, ~0ull, 0u, 1u, {}};
-
-static uint32_t div_up(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
-
-uint32_t blocks_for(int l, const SweepArgs& a) {
-    const uint64_t L = static_cast<uint64_t>(a.L);
-    const int mt = a.merge_tiles;
-    switch (l) {
-        case kLBondPotts: return a.model == SW_POTTS ? static_cast<uint32_t>(a.tiles_x * a.tiles_y) : 0u;
-        case kLBondClock: return a.model == SW_CLOCK ? static_cast<uint32_t>(a.tiles_x * a.tiles_y) : 0u;
-        case kLBlockMerge: return mt > 1 ? merge_blocks_x(a.tiles_x, mt) * merge_blocks_x(a.tiles_y, mt) : 0u;
-        case kLBorderMerge: return div_up((merge_blocks_x(a.tiles_x, mt) + merge_blocks_x(a.tiles_y, mt)) * L, 256);
-        case kLFlatten: return div_up((static_cast<uint64_t>(a.tiles_x) + a.tiles_y) * L, 256);
-        case kLFlip: return static_cast<uint32_t>(a.tiles_x * a.tiles_y);
-        case kLCounts: return count_blocks(a.L);
-        case kLCountSum: return 1u;
-        default: return 0u;
-    }
-}
-
-SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
-    SweepArgs a{};
-    a.spins = reinterpret_cast<int8_t*>(base + lay.spins);
-    a.flip_out = a.spins;
-    a.bond_r = reinterpret_cast<uint64_t*>(base + lay.bond_r);
-    a.bond_d = reinterpret_cast<uint64_t*>(base + lay.bond_d);
-    a.labels = reinterpret_cast<uint32_t*>(base + lay.labels);
-    a.canon = reinterpret_cast<uint32_t*>(base + lay.canon);
-    a.count_partial = reinterpret_cast<uint32_t*>(base + lay.count_partial);
-    a.border_roots = reinterpret_cast<uint32_t*>(base + lay.border_roots);
-    a.border_bonds = reinterpret_cast<uint64_t*>(base + lay.border_bonds);
-    a.table = reinterpret_cast<const uint32_t*>(base + lay.table);
-    a.ctl = reinterpret_cast<Control*>(base + lay.ctl);
-    a.count_row = nullptr;
-    a.L = p.L;
-    a.q = p.q;
-    a.model = p.model;
-    a.w64 = (p.L + 63) / 64;
-    a.tiles_x = (p.L + kTileW - 1) / kTileW;
-    a.tiles_y = (p.L + kTileH - 1) / kTileH;
-    a.tile_waves = (a.tiles_x * a.tiles_y < kSmallTiles) ? kWavesSmall : kWaves;
-    a.merge_tiles = kMergeTiles;
-    a.key0 = static_cast<uint32_t>(p.seed);
-    a.key1 = static_cast<uint32_t>(p.seed >> 32);
-    return a;
-}
-
-void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, const Sums& sums, sw_obs* out) {
-    std::memset(out, 0, sizeof *out);
-    out->sweeps_done = t;
-    out->samples = sums.samples;
-    for (int k = 0; k < 32; ++k) {
-        out->hist[k] = row[kRowHist + k];
-        out->pair_hist[k] = row[kRowPair + k];
-        if (p.model == SW_CLOCK) {
-            out->corr_hist[0][k] = row[kRowCorr1 + k];
-            out->corr_hist[1][k] = row[kRowCorr2 + k];
-        }
-    }
-    const Observables o = observables_of(p, row);
-    out->e_per_site = o.e;
-    out->m2 = o.m2;
-    out->g_quarter = o.g1;
-    out->g_half = o.g2;
-    if (sums.samples) {
-        const double n = static_cast<double>(sums.samples);
-        out->mean_e = sums.e / n;
-        out->mean_m2 = sums.m2 / n;
-        out->mean_m4 = sums.m4 / n;
-        out->binder_u = out->mean_m2 > 0.0 ? out->mean_m4 / (out->mean_m2 * out->mean_m2) : 0.0;
-        out->mean_g_quarter = sums.g1 / n;
-        out->mean_g_half = sums.g2 / n;
-        out->corr_ratio = out->mean_g_quarter != 0.0 ? out->mean_g_half / out->mean_g_quarter : 0.0;
-    }
-}
-
-}  // namespace host
-}  // namespace swmc
 
 struct sw_ctx {
     sw_lattice p{};
@@ -266,6 +39,9 @@ struct sw_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_state = nullptr, ev_count[2] = {nullptr, nullptr};
     uint64_t le_iterations = 0, le_sweeps = 0;
+    // per-sweep state hashes (SW_HASH) moved to the host, not yet read
+    std::vector<HashRecord> hashes;
+    std::vector<uint64_t> hash_host;
     int64_t prof_launches[kNumKernels] = {};
     double prof_ms[kNumKernels] = {};
 };
@@ -318,11 +94,24 @@ int check_ctx(sw_ctx* c) {
     return SW_OK;
 }
 
+// After a synchronisation: the control block's fault bits (a kernel met a
+// broken forest) make the context sticky.
+int check_fault(sw_ctx* c, Control* ctl_out = nullptr) {
+    Control ctl;
+    SW_HIP(c, hipMemcpy(&ctl, c->base + c->lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    if (ctl_out) *ctl_out = ctl;
+    const int st = fault_status(ctl.fault);
+    if (st) c->sticky = true;
+    return st;
+}
+
 // Fold count rows [0, rows) of the device ring into the running averages.
 int flush_ring(sw_ctx* c, int rows) {
     if (rows <= 0) return SW_OK;
     if (c->side) SW_HIP(c, hipStreamSynchronize(c->side));
     SW_HIP(c, hipStreamSynchronize(c->stream));
+    const int st = check_fault(c);
+    if (st) return st;
     c->ring_host.resize(static_cast<size_t>(rows) * kRowWords);
     SW_HIP(c, hipMemcpy(c->ring_host.data(), c->base + c->lay.ring, c->ring_host.size() * 8, hipMemcpyDeviceToHost));
     for (int r = 0; r < rows; ++r) {
@@ -403,7 +192,19 @@ int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_c
         e = hipMemcpyAsync(c->base + lay.table, c->table.data(), c->table.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_init(a, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return cleanup(fail(SW_EDEVICE, "sw_init: %s", hipGetErrorString(e)));
+    // the side stream of measured sweeps and its events (default priority),
+    // made here so that no measured call pays for them
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_state, hipEventDisableTiming);
+    for (auto& ev : c->ev_count)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (c->side) (void)hipStreamDestroy(c->side);
+        if (c->ev_state) (void)hipEventDestroy(c->ev_state);
+        for (auto& ev : c->ev_count)
+            if (ev) (void)hipEventDestroy(ev);
+        return cleanup(fail(SW_EDEVICE, "sw_init: %s", hipGetErrorString(e)));
+    }
     *out = c;
     return SW_OK;
 }
@@ -412,9 +213,37 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
     int st = check_ctx(c);
     if (st) return st;
     if (nsweeps < 0) return fail(SW_EINVAL, "nsweeps must be >= 0");
-    if (flags & ~(SW_MEASURE | SW_VERIFY | SW_PROFILE)) return fail(SW_EINVAL, "unknown flag bits");
+    if (flags & ~(SW_MEASURE | SW_VERIFY | SW_PROFILE | SW_HASH)) return fail(SW_EINVAL, "unknown flag bits");
     const bool measure = flags & SW_MEASURE;
     const bool profile = flags & SW_PROFILE;
+    const bool hash = flags & SW_HASH;
+    // Per-sweep hashes (SW_HASH): hash_sweep reads the forest after a sweep's
+    // border merge; rows of the device hash ring are moved to the host when
+    // the ring is full and at the end of the call.
+    int hrows = 0;
+    auto flush_hashes = [&]() -> int {
+        if (hrows == 0) return SW_OK;
+        SW_HIP(c, hipStreamSynchronize(c->stream));
+        Control ctl;
+        const int st2 = check_fault(c, &ctl);
+        if (st2) return st2;
+        c->hash_host.resize(2 * static_cast<size_t>(hrows));
+        SW_HIP(c, hipMemcpy(c->hash_host.data(), c->base + c->lay.hash_ring, c->hash_host.size() * 8,
+                            hipMemcpyDeviceToHost));
+        // every enqueued sweep has finished: the last record is the state ctl.t
+        for (int r = 0; r < hrows; ++r)
+            c->hashes.push_back({ctl.t - static_cast<uint64_t>(hrows - 1 - r), c->hash_host[2 * r],
+                                 c->hash_host[2 * r + 1]});
+        hrows = 0;
+        return SW_OK;
+    };
+    auto hash_sweep = [&](const SweepArgs& a) -> int {
+        if (!hash) return SW_OK;
+        const int st2 = timed(c, profile, kKHash, [&] { return launch_hash_sweep(a, static_cast<uint32_t>(hrows), c->stream); });
+        if (st2) return st2;
+        if (++hrows == kRing) return flush_hashes();
+        return SW_OK;
+    };
     int64_t* const ring = reinterpret_cast<int64_t*>(c->base + c->lay.ring);
     int rows = 0;
     auto next_row = [&](int64_t** row) -> int {
@@ -440,11 +269,6 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
     // call's final flip) waits for it, so counting overlaps the merges and
     // the next sweep's bond kernel.
     const bool overlap = measure && !profile && c->labeler == kUnionFind;
-    if (overlap && !c->side) {
-        SW_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        SW_HIP(c, hipEventCreateWithFlags(&c->ev_state, hipEventDisableTiming));
-        for (auto& ev : c->ev_count) SW_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    }
     bool pending[2] = {false, false};  // a count of spin buffer 0 / 1 may still run
     auto buffer_of = [&](const int8_t* p) { return p == spins0 ? 0 : 1; };
     auto before_write = [&](const int8_t* p) -> int {
@@ -503,6 +327,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
             c->le_sweeps += 1;
             st = timed(c, profile, kKLeRoots, [&] { return launch_le_roots(a, c->stream); });
             if (st) return st;
+            st = hash_sweep(a);
+            if (st) return st;
             st = timed(c, profile, kKFlip, [&] { return launch_flip(a, verify, c->stream); });
             if (st) return st;
             if (verify) c->have_canon = true;
@@ -511,6 +337,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
                 if (st) return st;
             }
         }
+        st = flush_hashes();
+        if (st) return st;
         return flush_ring(c, rows);
     }
     SweepArgs a = c->args;
@@ -542,6 +370,8 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         }
         st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(a, c->stream); });
         if (st) return st;
+        st = hash_sweep(a);
+        if (st) return st;
         // a verified sweep's canonical labels need the links; otherwise the
         // flatten leaves root words where the next flip looks
         a.root_copies = verify ? 0 : 1;
@@ -565,7 +395,27 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
     // later work on the context's stream comes after every count of the call
     for (int b = 0; b < 2; ++b)
         if (pending[b]) SW_HIP(c, hipStreamWaitEvent(c->stream, c->ev_count[b], 0));
+    st = flush_hashes();
+    if (st) return st;
     return flush_ring(c, rows);
+}
+
+int sw_read_hashes(sw_ctx* c, uint64_t* out, size_t cap, size_t* n) {
+    int st = check_ctx(c);
+    if (st) return st;
+    if (!n || (cap > 0 && !out)) return fail(SW_EINVAL, "bad output arrays");
+    SW_HIP(c, hipStreamSynchronize(c->stream));
+    st = check_fault(c);
+    if (st) return st;
+    const size_t k = c->hashes.size() < cap ? c->hashes.size() : cap;
+    for (size_t r = 0; r < k; ++r) {
+        out[3 * r] = c->hashes[r].t;
+        out[3 * r + 1] = c->hashes[r].hs;
+        out[3 * r + 2] = c->hashes[r].hl;
+    }
+    c->hashes.erase(c->hashes.begin(), c->hashes.begin() + static_cast<std::ptrdiff_t>(k));
+    *n = k;
+    return SW_OK;
 }
 
 int sw_measure(sw_ctx* c, sw_obs* out) {
@@ -575,12 +425,20 @@ int sw_measure(sw_ctx* c, sw_obs* out) {
     SweepArgs a = c->args;
     a.count_row = reinterpret_cast<int64_t*>(c->base + c->lay.scratch_row);
     SW_HIP(c, launch_counts(a, c->stream));
+    const uint32_t N = static_cast<uint32_t>(c->p.L) * static_cast<uint32_t>(c->p.L);
+    SW_HIP(c, launch_hash_state(a.spins, c->have_canon ? a.canon : nullptr, N, a.hash_partial, c->stream));
     int64_t row[kRowWords];
+    uint64_t h[2];
     Control ctl;
     SW_HIP(c, hipStreamSynchronize(c->stream));
+    st = check_fault(c, &ctl);
+    if (st) return st;
     SW_HIP(c, hipMemcpy(row, a.count_row, sizeof row, hipMemcpyDeviceToHost));
-    SW_HIP(c, hipMemcpy(&ctl, c->base + c->lay.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    SW_HIP(c, hipMemcpy(h, a.hash_partial + 2 * static_cast<size_t>(hash_state_blocks(N)), sizeof h,
+                        hipMemcpyDeviceToHost));
     fill_obs(c->p, row, ctl.t, c->sums, out);
+    out->hash_spins = h[0];
+    out->hash_labels = c->have_canon ? h[1] : 0u;
     return SW_OK;
 }
 
@@ -590,6 +448,8 @@ int sw_read_spins(sw_ctx* c, int8_t* host, size_t n) {
     const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
     if (!host || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
     SW_HIP(c, hipStreamSynchronize(c->stream));
+    st = check_fault(c);
+    if (st) return st;
     SW_HIP(c, hipMemcpy(host, c->base + c->lay.spins, N, hipMemcpyDeviceToHost));
     return SW_OK;
 }
@@ -601,6 +461,8 @@ int sw_read_labels(sw_ctx* c, int32_t* host, size_t n) {
     if (!host || n != N) return fail(SW_EINVAL, "n must be N = %zu", N);
     if (!c->have_canon) return fail(SW_ESTATE, "no sweep was run with SW_VERIFY");
     SW_HIP(c, hipStreamSynchronize(c->stream));
+    st = check_fault(c);
+    if (st) return st;
     SW_HIP(c, hipMemcpy(host, c->base + c->lay.canon, N * 4, hipMemcpyDeviceToHost));
     return SW_OK;
 }
@@ -798,6 +660,6 @@ const char* sw_strerror(int s) {
     }
 }
 
-const char* sw_last_error(void) { return g_last_error.c_str(); }
+const char* sw_last_error(void) { return last_error_text(); }
 
 }  // extern "C"

@@ -24,7 +24,8 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 def spin_hash(spins) -> int:
     """sum_i mix64((i << 8) | s_i) mod 2^64 with the SplitMix64 output function
-    (Steele, Lea & Flood 2014): an order-independent fingerprint of a state."""
+    (Steele, Lea & Flood 2014): an order-independent fingerprint of a state,
+    on the host (the server and `Lattice.measure` compute it on the device)."""
     s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1).view(np.uint8).astype(np.uint64)
     z = (np.arange(s.size, dtype=np.uint64) << np.uint64(8)) | s
     with np.errstate(over="ignore"):
@@ -161,9 +162,9 @@ def run_plain(trace, arrivals) -> dict:
             time.sleep(wait)
         lat = Lattice(c.L, c.q, c.model, T=c.T, J=c.J, seed=c.seed)
         lat.sweep(c.sweeps)
-        ob = lat.measure()  # synchronises
+        ob = lat.measure()  # synchronises; counts and the spin hash come from the device, as in the server
         done[i] = time.perf_counter() - t0
-        results[i] = {"spin_hash": spin_hash(lat.spins()), "hist": ob["hist"], "pair_hist": ob["pair_hist"],
+        results[i] = {"spin_hash": ob["hash_spins"], "hist": ob["hist"], "pair_hist": ob["pair_hist"],
                       "e": ob["e"], "m2": ob["m2"], "t": ob["t"]}
         lat.close()
     torch.cuda.synchronize()
