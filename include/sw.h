@@ -208,6 +208,39 @@ const char* sw_strerror(int status);
 const char* sw_last_error(void);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * sw_sweep_static runs nsweeps >= 0 sweeps of the lattice *p, as sw_sweep
+ * does, without a context and without allocating anything: no hipMalloc, no
+ * hipFree, no stream or event creation.  The label forest, bond masks,
+ * border records and control block live in one static device buffer of the
+ * library, SW_STATIC_SCRATCH_BYTES bytes on each GPU it runs on (sized for
+ * L <= SW_STATIC_MAX_L; held until the process ends).
+ *   spins:  device int8[L*L] (caller-owned, 16-byte aligned), the state at
+ *           sweep index t on entry; replaced in place by the state at sweep
+ *           t + nsweeps.
+ *   table:  device copy of the cutoff table of *p (sw_cutoff_table).
+ *   labels: device int32[L*L] (16-byte aligned) or NULL; if given (nsweeps >= 1), receives the
+ *           canonical labels (smallest site index of the cluster) of the
+ *           last sweep.
+ *   fault:  device uint32 or NULL; if given, receives 0, or the nonzero
+ *           fault bits of a kernel that found the label forest broken.
+ * Every kernel is enqueued on stream (NULL = the null stream); the call
+ * returns without waiting.  The results equal sw_init + sw_write_spins(t) +
+ * sw_sweep(nsweeps) bit for bit.  Errors: SW_EINVAL (invalid lattice,
+ * L > SW_STATIC_MAX_L, null spins or table, misaligned pointers, labels with
+ * nsweeps = 0) before
+ * any device work; SW_EDEVICE if a launch fails.
+ * All calls on one GPU share its buffer: calls that overlap in time on one
+ * GPU (different streams, or threads) race and corrupt each other; serialise
+ * them, e.g. on one stream. */
+#define SW_STATIC_MAX_L 1024
+#define SW_STATIC_SCRATCH_BYTES 4735232u
+int sw_sweep_static(const sw_lattice* p, int8_t* spins, uint64_t t, int32_t nsweeps, const uint32_t* table,
+                    int32_t* labels, uint32_t* fault, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: n independent lattices (replicas of any L, q, model, T, seed) swept
  * together.  Every phase of a sweep (Sec. 2 steps (1)-(3)) is one launch over
  * the workgroups of all replicas; one sweep's launches are captured once in a

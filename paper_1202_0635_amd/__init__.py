@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (SW_CLOCK, SW_HASH, SW_MEASURE, SW_NO_GRAPH, SW_POTTS, SW_PROFILE, SW_VERIFY, SwError, SwLattice,
                    SwObs, check)
 
-__all__ = ["Lattice", "Batch", "SwError", "critical_temperature", "cutoff_table", "state_bytes",
+__all__ = ["Lattice", "Batch", "SwError", "critical_temperature", "cutoff_table", "state_bytes", "sweep_static",
            "SW_MEASURE", "SW_VERIFY", "SW_PROFILE", "SW_NO_GRAPH", "SW_HASH"]
 
 MODELS = {"potts": SW_POTTS, "clock": SW_CLOCK}
@@ -49,6 +49,31 @@ def cutoff_table(L, q, model="potts", T=1.0, J=1.0) -> np.ndarray:
     out = np.zeros(n, dtype=np.uint32)
     check(_lib.lib().sw_cutoff_table(ctypes.byref(p), out.ctypes.data_as(ctypes.c_void_p), n), "sw_cutoff_table")
     return out
+
+
+STATIC_MAX_L = 1024
+
+
+def sweep_static(spins, L, q, model="potts", T=None, J=1.0, seed=0, t=0, nsweeps=1, table=None, labels=None,
+                 fault=None, stream=None):
+    """nsweeps sweeps of the state `spins` (a torch int8 CUDA tensor of L*L
+    sites at sweep index t, replaced in place) through sw_sweep_static, which
+    allocates no device memory.  table: torch CUDA tensor of the cutoff table
+    (int32 or uint32 words); labels: optional torch int32 CUDA tensor [L*L]
+    for the last sweep's canonical labels; fault: optional torch int32 CUDA
+    tensor [1].  Enqueued on `stream` (default: torch's current stream)."""
+    import torch
+
+    if T is None:
+        T = critical_temperature(model, q)
+    p = _lattice(L, q, model, T, J, seed)
+    s = stream if stream is not None else torch.cuda.current_stream(spins.device)
+
+    def ptr(x):
+        return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+    check(_lib.lib().sw_sweep_static(ctypes.byref(p), ptr(spins), int(t), int(nsweeps), ptr(table), ptr(labels),
+                                     ptr(fault), ctypes.c_void_p(s.cuda_stream)), "sw_sweep_static")
 
 
 class Lattice:

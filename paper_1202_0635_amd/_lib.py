@@ -97,6 +97,8 @@ SIGNATURES = {
     "sw_labeler_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "sw_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "sw_free": (None, [ctypes.c_void_p]),
+    "sw_sweep_static": (ctypes.c_int, [ctypes.POINTER(SwLattice), ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sw_batch_bytes": (ctypes.c_size_t, [ctypes.POINTER(SwLattice), ctypes.c_int32]),
     "sw_batch_init": (ctypes.c_int, [ctypes.POINTER(SwLattice), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libswmc.so")
 
-SOURCES = ["sw_kernels.hip", "sw_host.cpp", "sw_runtime.cpp", "sw_batch.cpp", "sw_server.cpp"]
+SOURCES = ["sw_kernels.hip", "sw_static.hip", "sw_host.cpp", "sw_runtime.cpp", "sw_batch.cpp", "sw_server.cpp"]
 HEADERS = ["sw_internal.hpp", "sw_device.hpp", "sw_host.hpp", "sw_sched.hpp"]
 
 HIPCC_FLAGS = [

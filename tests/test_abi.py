@@ -93,3 +93,19 @@ def test_null_context_calls_fail_cleanly(swlib):
     lib.sw_free(None)
     for st in (0, -1, -2, -3, -4, -5, -6, 7):
         assert lib.sw_strerror(st)
+
+
+def test_static_entry_rejects_before_device_work(swlib):
+    """sw_sweep_static checks its arguments before any HIP call (no GPU here)."""
+    lib = swlib.lib()
+    dummy = ctypes.c_void_p(0x1000)
+    big = _lattice(swlib, 1025, 2, 0, 1.0)
+    assert lib.sw_sweep_static(ctypes.byref(big), dummy, 0, 1, dummy, None, None, None) == swlib.SW_EINVAL
+    assert b"1024" in lib.sw_last_error()
+    ok = _lattice(swlib, 64, 2, 0, 1.0)
+    assert lib.sw_sweep_static(ctypes.byref(ok), None, 0, 1, dummy, None, None, None) == swlib.SW_EINVAL
+    assert lib.sw_sweep_static(ctypes.byref(ok), dummy, 0, -1, dummy, None, None, None) == swlib.SW_EINVAL
+    assert lib.sw_sweep_static(ctypes.byref(ok), dummy, 0, 0, dummy, dummy, None, None) == swlib.SW_EINVAL
+    bad = _lattice(swlib, 64, 1, 0, 1.0)
+    assert lib.sw_sweep_static(ctypes.byref(bad), dummy, 0, 1, dummy, None, None, None) == swlib.SW_EINVAL
+    assert lib.sw_sweep_static(ctypes.byref(ok), ctypes.c_void_p(0x1001), 0, 1, dummy, None, None, None) == swlib.SW_EINVAL
