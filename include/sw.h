@@ -64,8 +64,10 @@ enum {
 
 /* One lattice.  Potts: H = -J sum_<ij> (delta(S_i,S_j) - 1) (Sec. 2, Eq. 1);
  * clock: H = -J sum_<ij> S_i . S_j with S = (cos 2 pi k/q, sin 2 pi k/q) (Sec. 4).
- * Valid: 2 <= L <= 46340, 2 <= q <= 32, model in {SW_POTTS, SW_CLOCK},
- * 0 < T, 0 < J (finite).  reserved must be 0. */
+ * Valid: 2 <= q <= 32, model in {SW_POTTS, SW_CLOCK}, 0 < T, 0 < J (finite),
+ * reserved 0, and 2 <= L <= 65535 for a single lattice (sw_init; site indices
+ * below 2^32), 2 <= L <= 46340 for batches, the server, sw_sweep_static and
+ * the label-equivalence labelers (site indices below 2^31). */
 typedef struct {
     int32_t L, q, model, reserved;
     double T, J;
@@ -173,20 +175,16 @@ int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n);
 int sw_profile_read(sw_ctx* c, const char** names, int64_t* launches, double* total_ms,
                     int32_t cap, int32_t* nk);
 
-/* Merge schedule: 1 = one device-wide border kernel; 2 or 4 (default 4) = the
- * inner borders of blocks of that many tiles per side are first joined inside
- * one workgroup, in LDS.  Other values: SW_EINVAL.  Results do not depend on it
- * (canonical labels are unique); only the time does. */
-int sw_set_schedule(sw_ctx* c, int32_t merge_tiles);
 /* Waves per 64 x 64 tile of the bond kernel: 4 (16 rows each) or 8 (8 rows
  * each).  The default is 8 for lattices of fewer than 3072 tiles (L <= 3520),
  * where 4-wave workgroups leave the chip's SIMDs short of waves, else 4.
  * Other values: SW_EINVAL.  Results do not depend on it; only the time does. */
 int sw_set_tile_waves(sw_ctx* c, int32_t waves);
-/* Autotuner: times `sweeps` sweeps under every schedule from the current state,
- * restores the state (spins and sweep index) after each, keeps the fastest and
- * returns it in *merge_tiles.  Allocates a temporary snapshot buffer. */
-int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles);
+/* Autotuner: times `sweeps` sweeps with 4 and with 8 waves per tile from the
+ * current state (three rounds, each choice's fastest counts), restores the
+ * state (spins and sweep index) after each, keeps the faster and returns it in
+ * *waves.  Allocates a temporary snapshot buffer. */
+int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* waves);
 
 /* The cluster labeler (Sec. 3).  SW_LABEL_UNION_FIND (default): tile-local
  * union-find in LDS, then lock-free unions across tile borders.

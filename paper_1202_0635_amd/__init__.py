@@ -133,7 +133,8 @@ class Lattice:
     def labels(self) -> np.ndarray:
         out = np.zeros(self.N, dtype=np.int32)
         check(_lib.lib().sw_read_labels(self._ctx, out.ctypes.data_as(ctypes.c_void_p), self.N), "sw_read_labels")
-        return out.reshape(self.L, self.L)
+        # site indices reach 2^31 above L = 46340: the words are unsigned
+        return out.reshape(self.L, self.L).view(np.uint32) if self.L > 46340 else out.reshape(self.L, self.L)
 
     def bonds(self):
         r = np.zeros(self.N, dtype=np.uint8)
@@ -158,11 +159,11 @@ class Lattice:
         return self._arena[off: off + self.N].view(torch.int8).view(self.L, self.L)
 
     def profile(self) -> dict:
-        names = (ctypes.c_char_p * 16)()
-        launches = (ctypes.c_int64 * 16)()
-        ms = (ctypes.c_double * 16)()
+        names = (ctypes.c_char_p * 32)()
+        launches = (ctypes.c_int64 * 32)()
+        ms = (ctypes.c_double * 32)()
         nk = ctypes.c_int32()
-        check(_lib.lib().sw_profile_read(self._ctx, names, launches, ms, 16, ctypes.byref(nk)), "sw_profile_read")
+        check(_lib.lib().sw_profile_read(self._ctx, names, launches, ms, 32, ctypes.byref(nk)), "sw_profile_read")
         return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(nk.value)}
 
     LABELERS = {"union_find": 0, "hawick": 1, "kalentev": 2}
@@ -178,10 +179,6 @@ class Lattice:
         it, sw = ctypes.c_uint64(), ctypes.c_uint64()
         check(_lib.lib().sw_labeler_stats(self._ctx, ctypes.byref(it), ctypes.byref(sw)), "sw_labeler_stats")
         return {"iterations": int(it.value), "sweeps": int(sw.value)}
-
-    def set_schedule(self, merge_tiles: int):
-        check(_lib.lib().sw_set_schedule(self._ctx, int(merge_tiles)), "sw_set_schedule")
-        return self
 
     def set_tile_waves(self, waves: int):
         """Waves per 64 x 64 tile of the bond kernel (4 or 8); results do not depend on it."""

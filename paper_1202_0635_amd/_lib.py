@@ -91,7 +91,6 @@ SIGNATURES = {
     "sw_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
-    "sw_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_set_tile_waves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_set_labeler": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sw_labeler_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),

@@ -30,9 +30,9 @@ int fail(int status, const char* fmt, ...) {
     return status;
 }
 
-bool lattice_ok(const sw_lattice* p, std::string* why) {
+bool lattice_ok(const sw_lattice* p, std::string* why, int max_side) {
     if (!p) return *why = "null sw_lattice", false;
-    if (p->L < 2 || p->L > 46340) return *why = "L must be in [2, 46340]", false;
+    if (p->L < 2 || p->L > max_side) return *why = "L must be in [2, " + std::to_string(max_side) + "]", false;
     if (p->q < 2 || p->q > 32) return *why = "q must be in [2, 32]", false;
     if (p->model != SW_POTTS && p->model != SW_CLOCK) return *why = "model must be SW_POTTS or SW_CLOCK", false;
     if (p->reserved != 0) return *why = "reserved must be 0", false;
@@ -127,7 +127,12 @@ Layout layout_of(const sw_lattice& p, bool with_pair) {
     l.table = o; o += up(table_entries(p) * 4);
     if (with_pair) {
         l.spins2 = o; o += up(N);
-        l.labels2 = o; o += up(N * 4);
+        for (int b = 0; b < 2; ++b) {
+            l.codes[b] = o; o += up(N * 2);
+            l.nodes[b] = o; o += up(tiles * kSlotsPerTile * 8);
+            l.nslots[b] = o; o += up(tiles * 4);
+        }
+        l.border_slots = o; o += up(tiles * 4 * kTileW);
     }
     l.total = o;
     return l;
@@ -226,6 +231,7 @@ SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     a.tiles_y = (p.L + kTileH - 1) / kTileH;
     a.tile_waves = (a.tiles_x * a.tiles_y < kSmallTiles) ? kWavesSmall : kWaves;
     a.merge_tiles = kMergeTiles;
+    a.node_cap = static_cast<uint32_t>(a.tiles_x) * static_cast<uint32_t>(a.tiles_y) * kSlotsPerTile;
     a.key0 = static_cast<uint32_t>(p.seed);
     a.key1 = static_cast<uint32_t>(p.seed >> 32);
     return a;

@@ -15,7 +15,9 @@ namespace host {
 // Record a status with a formatted reason (thread-local, read by sw_last_error).
 int fail(int status, const char* fmt, ...);
 const char* last_error_text();
-bool lattice_ok(const sw_lattice* p, std::string* why);
+// max_side: kMaxSide for single-lattice contexts (two-level labels), else
+// kMaxSideFlagged (one-level label words with a root flag).
+bool lattice_ok(const sw_lattice* p, std::string* why, int max_side = kMaxSideFlagged);
 
 double turn_cos(int n, int q);
 double turn_sin(int n, int q);
@@ -27,10 +29,12 @@ size_t up(size_t v);
 
 struct Layout {
     size_t ctl, spins, bond_r, bond_d, labels, canon, count_partial, border_roots, border_bonds, ring, scratch_row,
-        hash_ring, hash_partial, table, spins2, labels2, total;
+        hash_ring, hash_partial, table, spins2, codes[2], nodes[2], nslots[2], border_slots, total;
 };
-// Arena layout; with_pair adds the second spin and label buffers that the
-// fused flip-and-bond kernel alternates with (single-lattice contexts).
+// Arena layout; with_pair adds what single-lattice contexts use beside the
+// one-level forest: the two-level labels (codes, node forests and node counts,
+// two of each, alternating from sweep to sweep), the border records of slots,
+// and a second spin buffer for the states of measured sweeps.
 Layout layout_of(const sw_lattice& p, bool with_pair = false);
 
 struct Observables {

@@ -48,6 +48,23 @@ constexpr uint32_t kLdsWalkCap = kTileW * kTileH;       // a tile forest in LDS 
 constexpr uint32_t kGlobalWalkCap = 1u << 22;           // the global forest
 enum FaultBits : uint32_t { kFaultLds = 1u, kFaultGlobal = 2u, kFaultFlip = 4u, kFaultHash = 8u };
 
+// Two-level labels of single lattices.  Per site, a 16-bit code: a site
+// whose tile-local component stays off the tile's perimeter holds its new
+// value (bit 15 clear); any other site holds kCodeNode | slot (bits 0-7),
+// plus (clock model) its old value in bits 8-12.  The components that reach
+// a tile's perimeter (at most 252 per tile) are the nodes of a global forest:
+// node tile * kSlotsPerTile + slot is a 64-bit word whose high half is the
+// component's smallest site index (its key) and whose low half is either
+// kNodeRoot | draw (a cluster root) or the index of a node with a smaller key.
+constexpr uint32_t kSlotsPerTile = 256;
+constexpr uint32_t kCodeNode = 0x8000u;
+constexpr uint32_t kNodeRoot = 0x80000000u;
+// Largest side of a single lattice (site indices stay below 2^32); batches,
+// the server, the static entry point and the label-equivalence labelers keep
+// root flags in 32-bit label words and stop at kMaxSideFlagged.
+constexpr int kMaxSide = 65535;
+constexpr int kMaxSideFlagged = 46340;
+
 // Per-tile border record written by the bond kernel.  Edge e of border_roots:
 // 0 right column, 1 bottom row, 2 left column, 3 top row (the last valid
 // column / row of a ragged tile).  Masks: bit = row (columns) or column (rows).
@@ -81,8 +98,6 @@ static_assert(sizeof(Control) == 64, "control block is one 64-byte line");
 struct SweepArgs {
     int8_t* spins;        // [N] the state the bond kernel reads (and the fused kernel writes)
     int8_t* flip_out;     // [N] where k_flip writes the new state (usually spins)
-    const uint32_t* labels_prev;  // fused kernel: the previous sweep's forest
-    const int8_t* spins_prev;     // fused kernel: the state before the previous sweep
     uint64_t* bond_r;     // [L][w64]: bit x%64 of word x/64 = right bond of (x,y)
     uint64_t* bond_d;     // [L][w64]: down bonds
     uint32_t* labels;     // [N] union-find forest with root words (kRootFlag)
@@ -93,6 +108,18 @@ struct SweepArgs {
     uint32_t* count_partial;  // [count_blocks(L)][kRowWords]: each count workgroup's bins
     uint32_t* border_roots;   // [tiles][4][64]: tile-local root (site index) of each edge site
     uint64_t* border_bonds;   // [tiles][kBorderMasks]: the bond bits the border joins read
+    // two-level labels (single lattices; the previous sweep's arrays are read
+    // by the fused kernel)
+    uint16_t* codes;              // [N] per-site codes of this sweep
+    const uint16_t* codes_prev;   // [N] the previous sweep's
+    uint64_t* nodes;              // [tiles][kSlotsPerTile] this sweep's node forest
+    const uint64_t* nodes_prev;
+    uint32_t* nslots;             // [tiles] nodes per tile
+    const uint32_t* nslots_prev;
+    uint8_t* border_slots;        // [tiles][4][64] slot of each perimeter site (edges as border_roots)
+    uint32_t* lroot;              // [N] or null: tile-local root (site index) of every site
+    int8_t* spins_out;            // or null: the fused kernel also stores the state it computed
+    uint32_t node_cap;            // nodes of the forest: a walk longer than this met a broken forest
     uint64_t* hash_ring;      // [kRing][2]: per-sweep state hashes (spins, canonical labels)
     uint64_t* hash_partial;   // [hash_blocks(L)][2]: each hash workgroup's sums
     int L, q, model, w64;
@@ -109,9 +136,15 @@ struct SweepArgs {
 // Launch wrappers (defined in sw_kernels.hip).
 hipError_t launch_init(const SweepArgs& a, hipStream_t s);
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s);
-// The previous sweep's flip (from labels_prev, spins_prev) fused with this
-// sweep's bond kernel: writes the flipped state to spins, then as k_bond_local.
-hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s);
+// Two-level labels: the bond kernel writing codes and nodes (fused: from the
+// previous sweep's codes and node forest instead of spins), the merge of the
+// node forests across tile borders (also advances the sweep index), the last
+// sweep's flip into flip_out (and canonical labels into canon when verify),
+// and the per-sweep hashes read from codes, lroot and the merged forest.
+hipError_t launch_code_bond(const SweepArgs& a, bool fused, hipStream_t s);
+hipError_t launch_node_merge(const SweepArgs& a, hipStream_t s);
+hipError_t launch_code_flip(const SweepArgs& a, bool verify, hipStream_t s);
+hipError_t launch_code_hash(const SweepArgs& a, uint32_t row, hipStream_t s);
 hipError_t launch_block_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_border_merge(const SweepArgs& a, hipStream_t s);
 hipError_t launch_flatten(const SweepArgs& a, hipStream_t s);
@@ -168,7 +201,8 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
 
 enum KernelId {
     kKBondLocal, kKBlockMerge, kKBorderMerge, kKFlatten, kKFlip, kKCounts, kKFlipBond,
-    kKBondsOnly, kKLeIteration, kKLeRoots, kKHash, kNumKernels
+    kKBondsOnly, kKLeIteration, kKLeRoots, kKHash,
+    kKCodeBond, kKCodeFlipBond, kKNodeMerge, kKCodeFlip, kNumKernels
 };
 extern const char* const kKernelNames[kNumKernels];
 

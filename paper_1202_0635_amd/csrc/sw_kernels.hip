@@ -1,24 +1,35 @@
 // HIP kernels of the Swendsen-Wang sweep for gfx950 (wave64, LDS union-find).
 //
 // One sweep (Sec. 2 steps (1)-(3); the GPU organisation of Sec. 3 is replaced
-// by a non-iterative union-find):
-//   k_bond_local    per 64 x 64 tile: FK bonds from Philox draws, row runs by
+// by a non-iterative union-find).  Single lattices use two-level labels:
+//   k_code_bond     per 64 x 64 tile: FK bonds from Philox draws, row runs by
 //                   wave ballots, a Hoshen-Kopelman pass per wave and unions
-//                   in an LDS forest; tile-local roots written to the global
-//                   label forest with their cluster draw; per-tile border
-//                   records (edge roots and bond masks).
-//   k_flip_bond     the same for every sweep of a call after its first, with
-//                   the previous sweep's flip fused in (spins and labels
-//                   alternate between two buffers).
+//                   in an LDS forest.  Every tile-local component draws its
+//                   cluster value; a component off the tile's perimeter writes
+//                   its sites' new values straight into their 16-bit codes,
+//                   one that reaches the perimeter becomes a node of the
+//                   global forest (a slot of the tile) and its sites' codes
+//                   name the slot.  Border records hold the perimeter sites'
+//                   slots and the bond masks.  From a call's second sweep on,
+//                   the kernel takes the state from the previous sweep's codes
+//                   and node forest (the flip of that sweep fused in).
+//   k_node_merge    the tile borders and the torus wrap: lock-free unions of
+//                   node roots, the larger key (smallest site index of the
+//                   component) linked under the smaller by compare-and-swap.
+//   k_code_flip     the last sweep of a call: codes and merged nodes to spins
+//                   (and canonical labels in verify mode).
+//   k_code_hash     per-sweep state hashes from codes and merged nodes.
+// Batches and the static entry point use one-level labels (a 32-bit forest
+// over all sites with root words):
+//   k_bond_local    the same tile kernel writing the label forest and border
+//                   records of edge roots; tile-local roots hold their draw.
 //   k_block_merge   (schedules 2 and 4) the inner borders of blocks of tiles,
 //                   joined in LDS.
-//   k_border_merge  the remaining tile borders and the torus wrap: lock-free
-//                   unions of global roots, the larger index linked under the
-//                   smaller by compare-and-swap.
+//   k_border_merge  the remaining tile borders and the wrap, as k_node_merge.
 //   k_flatten       every linked tile-local root gets its cluster's root word
 //                   (or, for a verified sweep, a link straight to the root).
-//   k_flip          the last sweep of a call: each site reaches its root word
-//                   and takes the cluster's value (Potts) or reflection (clock).
+//   k_flip          each site reaches its root word and takes the cluster's
+//                   value (Potts) or reflection (clock).
 //   k_counts        measured sweeps: n[k], neighbour differences and, for the
 //                   clock model, the correlation counts at L/4 and L/2.
 // The paper's own label-equivalence labelers (k_bonds_only, k_le_*) are kept
@@ -30,7 +41,8 @@ namespace swmc {
 
 const char* const kKernelNames[kNumKernels] = {"k_bond_local", "k_block_merge",   "k_border_merge", "k_flatten",
                                                "k_flip",       "k_counts",        "k_flip_bond",    "k_bonds_only",
-                                               "k_le_iteration", "k_le_roots",    "k_hash"};
+                                               "k_le_iteration", "k_le_roots",    "k_hash",
+                                               "k_code_bond",    "k_code_flip_bond", "k_node_merge", "k_code_flip"};
 
 namespace {
 
@@ -45,7 +57,7 @@ __device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) {
 // A walk that has taken more steps than its forest has nodes has met a broken
 // forest (links must point to smaller indices): it records a fault bit in the
 // control block and stops, so a kernel ends instead of looping.
-__device__ __noinline__ void record_fault(Control* ctl, uint32_t bit) {
+__device__ __forceinline__ void record_fault(Control* ctl, uint32_t bit) {
     __hip_atomic_fetch_or(&ctl->fault, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -262,18 +274,6 @@ __device__ __forceinline__ int flipped(uint32_t root_word, int old, int m, int q
     return v;
 }
 
-__device__ __forceinline__ uint32_t root_word_of(const uint32_t* lab, uint32_t i, Control* ctl) {
-    uint32_t w = lab[i];
-    for (uint32_t n = 0; !(w & kRootFlag); ++n) {
-        if (n >= kGlobalWalkCap) {
-            record_fault(ctl, kFaultFlip);
-            break;
-        }
-        w = lab[w];
-    }
-    return w;
-}
-
 // ---------------------------------------------------------------------------
 // Bonds + tile-local labeling.  Lane = column; each wave owns kTileH/4
 // consecutive rows.  Each spin is loaded once: its right neighbour comes from
@@ -284,18 +284,55 @@ __device__ __forceinline__ uint32_t root_word_of(const uint32_t* lab, uint32_t i
 // collected in a tile-wide list and resolved with one draw per tied site.
 // ---------------------------------------------------------------------------
 struct BondShared {
-    uint32_t P[kTileH * kTileW];          // tie list, then the tile forest, then root lists
+    uint32_t P[kTileH * kTileW];          // tie list, then the tile forest, then per-root records
     uint64_t raw_r[kTileH];               // right-bond masks of the tile's rows
     uint64_t raw_d[kTileH];               // down-bond masks
     alignas(16) uint8_t halo[kTileH];     // spins of the column right of the tile
+    uint16_t edge[4][kTileW];             // codes: tile-local roots of the perimeter sites
+    uint8_t tbl[kSlotsPerTile];           // codes: the previous sweep's draw of each node of the tile
     uint32_t ntie;
+    uint32_t nslots;
 };
+
+// Where the bond kernel takes the state from, and what it writes.
+enum BondSource { kFromSpins = 0, kFromCodes = 1 };
+enum BondOutput { kWriteLabels = 0, kWriteCodes = 1, kWriteBonds = 2 };
+
+// Perimeter mark of a per-root record in the tile forest (code output): the
+// record's low half then holds the mark and the component's slot, else the
+// root's draw; the high half of the forest words of a wave's rows holds that
+// wave's list of roots while they draw.
+constexpr uint32_t kMarkPerimeter = 0x8000u;
+
+// Draw of the root word of node n in a finished node forest.
+__device__ __forceinline__ uint32_t node_root_low(const uint64_t* nodes, uint32_t n, const SweepArgs& a) {
+    uint64_t w = nodes[n];
+    for (uint32_t k = 0; !(static_cast<uint32_t>(w) & kNodeRoot); ++k) {
+        if (k >= a.node_cap) {
+            record_fault(a.ctl, kFaultGlobal);
+            return kNodeRoot;
+        }
+        w = nodes[min(static_cast<uint32_t>(w), a.node_cap - 1u)];  // (clamped: a broken forest stays in bounds)
+    }
+    return static_cast<uint32_t>(w);
+}
+
+// The state after the previous sweep at site j (row y, column xx) from its
+// code and the previous node forest (m: that sweep's mirror).
+template <bool kClock>
+__device__ __forceinline__ int site_from_code(const SweepArgs& a, uint32_t code, int y, int xx, int m) {
+    if (!(code & kCodeNode)) return static_cast<int>(code & 31u);
+    const uint32_t tile = static_cast<uint32_t>((y >> 6) * a.tiles_x + (xx >> 6));
+    const uint32_t v = node_root_low(a.nodes_prev, tile * kSlotsPerTile + (code & 0xFFu), a);
+    return kClock ? flipped<true>(v, static_cast<int>((code >> 8) & 31u), m, a.q) : static_cast<int>(v & 0xFFu);
+}
 
 // kFull: the tile lies inside the lattice (no column or row beyond L), which
 // removes the bounds tests from every row.
-template <int kModel, bool kFused, bool kFull, bool kBondsOnly, int kW>
+template <int kModel, int kSrc, int kOut, bool kFull, int kW>
 __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty, BondShared& sh) {
     constexpr bool kClock = kModel == 1;
+    constexpr bool kFused = kSrc == kFromCodes;
     constexpr int RPW = kTileH / kW;  // rows per wave (kW waves per tile)
     static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
     uint32_t* const P = sh.P;
@@ -314,8 +351,8 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     const int L = a.L, q = a.q;
     const int x0 = tx * kTileW, y0 = ty * kTileH;
     const int x = x0 + lane;
-    // Site indices stay below 2^31 (L <= 46340), so 32-bit arithmetic with
-    // 24-bit multiplies (L < 2^16) replaces 64-bit address products.
+    // Site indices stay below 2^32 (L < 2^16), so 32-bit arithmetic with
+    // 24-bit multiplies replaces 64-bit address products.
     const uint32_t tile_base = __umul24(y0, L) + static_cast<uint32_t>(x0);
     const size_t tile = static_cast<size_t>(ty) * a.tiles_x + tx;
     const bool col_ok = kFull || x < L;
@@ -334,13 +371,16 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // Cutoffs of this sweep: Potts needs only the equal-spin cutoff; the clock
     // model reads the q x q slice of its mirror m from LDS.
     const uint32_t c_eq = a.table[0];
+    const int m_cur = kClock ? mirror_of(t, q, k0, k1) : 0;
     if (kClock) {
-        const int m = mirror_of(t, q, k0, k1);
-        const uint32_t* src = a.table + static_cast<size_t>(m) * q * q;
+        const uint32_t* src = a.table + static_cast<size_t>(m_cur) * q * q;
         for (int k = threadIdx.x; k < q * q; k += kW * 64) cut[k] = src[k];
-        if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->mirror = static_cast<uint32_t>(m);
+        if (tx == 0 && ty == 0 && threadIdx.x == 0) a.ctl->mirror = static_cast<uint32_t>(m_cur);
     }
-    if (threadIdx.x == 0) ntie = 0;
+    if (threadIdx.x == 0) {
+        ntie = 0;
+        sh.nslots = 0;
+    }
     // Fused kernel: the spins this tile reads are the previous sweep's flip of
     // the previous state (mirror of sweep t - 1 for the clock model).
     const int m_prev = (kFused && kClock) ? mirror_of(t - 1, q, k0, k1) : 0;
@@ -362,40 +402,73 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         return ((!kFull || r == RPW) && yr == L) ? 0 : yr;
     };
     auto row_ok = [&](int r) -> bool { return kFull || (col_ok && y_base + r <= L); };
+    uint32_t cw[RPW + 1];  // fused: the previous codes of this lane's sites
     if (kFused) {
-        // the paths of the RPW + 1 sites of this lane (and of its halo site
-        // in wave 0) are followed together
-        uint32_t w[RPW + 2];
+        // The loads that depend on nothing are issued first: this lane's
+        // previous codes, the halo site's, and for thread k below the tile's
+        // node count the word of node k.  Then the walks to node roots advance
+        // together, one load each per step: node k's (its draw goes to LDS for
+        // this tile's sites), the halo site's and that of the one row of the
+        // strip that lies in another tile (the row below the strip, in the
+        // tile below or row 0 through the wrap, or in a ragged tile the
+        // wrapped row L), whose nodes lie in other tiles' forests.
+        const uint32_t ns = min(a.nslots_prev[tile], kSlotsPerTile);
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) {
-            const uint32_t* row = a.labels_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0));
-            w[r] = row_ok(r) ? row[ulane] : kRootFlag;
+            const uint16_t* row = a.codes_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0));
+            cw[r] = row_ok(r) ? row[ulane] : 0u;
         }
-        w[RPW + 1] = halo_lane ? a.labels_prev[ih] : kRootFlag;
-        // the previous forest holds root words at its roots and copies of them
-        // at its linked tile-local roots, and every other site names its
-        // tile-local root: one more load reaches a root word.  Every lane
-        // loads (a root word's lane reads site 0 and keeps its own word), so
-        // the RPW + 2 loads are issued back to back and waited for once.
-        uint32_t w2[RPW + 2];
-#pragma unroll
-        for (int r = 0; r <= RPW + 1; ++r) w2[r] = a.labels_prev[(w[r] & kRootFlag) ? 0u : w[r]];
-#pragma unroll
-        for (int r = 0; r <= RPW + 1; ++r) w[r] = (w[r] & kRootFlag) ? w[r] : w2[r];
-        if (wave == 0)
-            halo[lane] = halo_lane ? static_cast<uint8_t>(flipped<kClock>(w[RPW + 1], kClock ? a.spins_prev[ih] : 0, m_prev, q)) : 0;
-        // clock: the old spins, all loaded before the first store of a new
-        // spin (the two buffers could alias as far as the compiler knows)
-        int sp[RPW + 1];
+        const uint32_t hc = halo_lane ? static_cast<uint32_t>(a.codes_prev[ih]) : 0u;
+        const bool t_walk = threadIdx.x < ns;
+        uint64_t tw = t_walk ? a.nodes_prev[static_cast<uint32_t>(tile) * kSlotsPerTile + threadIdx.x] : kNodeRoot;
+        int rf = -1;  // uniform
 #pragma unroll
         for (int r = 0; r <= RPW; ++r)
-            sp[r] = (kClock && row_ok(r)) ? (a.spins_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0)))[ulane] : 0;
+            if ((!kFull || r == RPW) && y_base + r <= L && (row_of(r) >> 6) != ty) rf = r;
+        uint32_t fc = 0u;
 #pragma unroll
-        for (int r = 0; r <= RPW; ++r) {
-            const uint32_t rb = __umul24(row_of(r), L) + static_cast<uint32_t>(x0);
-            sreg[r] = row_ok(r) ? flipped<kClock>(w[r], sp[r], m_prev, q) : 0;
-            // the new state of this wave's own rows
-            if (r < RPW && (kFull || (col_ok && y_base + r < L))) (a.spins + rb)[ulane] = static_cast<int8_t>(sreg[r]);
+        for (int r = 0; r <= RPW; ++r)
+            if (r == rf && row_ok(r)) fc = cw[r];
+        const int yf = (rf >= 0) ? row_of(rf) : 0;
+        const uint32_t fn = static_cast<uint32_t>((yf >> 6) * a.tiles_x + (x >> 6)) * kSlotsPerTile + (fc & 0xFFu);
+        const uint32_t hn = static_cast<uint32_t>((yh >> 6) * a.tiles_x + (xh >> 6)) * kSlotsPerTile + (hc & 0xFFu);
+        uint64_t fw = (fc & kCodeNode) ? a.nodes_prev[min(fn, a.node_cap - 1u)] : kNodeRoot;
+        uint64_t hw = (hc & kCodeNode) ? a.nodes_prev[min(hn, a.node_cap - 1u)] : kNodeRoot;
+        for (uint32_t k = 0; !(static_cast<uint32_t>(tw) & static_cast<uint32_t>(fw) & static_cast<uint32_t>(hw) & kNodeRoot);
+             ++k) {
+            if (k >= a.node_cap) {
+                record_fault(a.ctl, kFaultGlobal);
+                tw = fw = hw = kNodeRoot;
+                break;
+            }
+            // (clamped: a broken forest stays in bounds)
+            if (!(static_cast<uint32_t>(tw) & kNodeRoot)) tw = a.nodes_prev[min(static_cast<uint32_t>(tw), a.node_cap - 1u)];
+            if (!(static_cast<uint32_t>(fw) & kNodeRoot)) fw = a.nodes_prev[min(static_cast<uint32_t>(fw), a.node_cap - 1u)];
+            if (!(static_cast<uint32_t>(hw) & kNodeRoot)) hw = a.nodes_prev[min(static_cast<uint32_t>(hw), a.node_cap - 1u)];
+        }
+        if (t_walk) sh.tbl[threadIdx.x] = static_cast<uint8_t>(tw);
+        // the state at a site from its code and, for a node's site, the root word
+        auto value_of = [&](uint32_t c, uint64_t w) -> int {
+            if (!(c & kCodeNode)) return static_cast<int>(c & 31u);
+            const uint32_t v = static_cast<uint32_t>(w) & 0xFFu;
+            return kClock ? flipped<true>(v, static_cast<int>((c >> 8) & 31u), m_prev, q) : static_cast<int>(v);
+        };
+        const int sf = value_of(fc, fw);
+        if (wave == 0) halo[lane] = halo_lane ? static_cast<uint8_t>(value_of(hc, hw)) : 0;
+        __syncthreads();  // the node draws, the halo and the cutoffs in LDS
+        auto own = [&](uint32_t c) -> int {
+            if (!(c & kCodeNode)) return static_cast<int>(c & 31u);
+            const uint32_t v = sh.tbl[c & 0xFFu];
+            return kClock ? flipped<true>(v, static_cast<int>((c >> 8) & 31u), m_prev, q) : static_cast<int>(v);
+        };
+#pragma unroll
+        for (int r = 0; r <= RPW; ++r) sreg[r] = !row_ok(r) ? 0 : (r == rf) ? sf : own(cw[r]);
+        if (a.spins_out) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const uint32_t rb = __umul24(row_of(r), L) + static_cast<uint32_t>(x0);
+                if (kFull || (col_ok && y_base + r < L)) (a.spins_out + rb)[ulane] = static_cast<int8_t>(sreg[r]);
+            }
         }
     } else {
 #pragma unroll
@@ -403,8 +476,17 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             sreg[r] = row_ok(r) ? (a.spins + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0)))[ulane] : 0;
         }
     }
-    __syncthreads();  // halo and cutoffs in LDS
+    if (!kFused) __syncthreads();  // halo and cutoffs in LDS (the fused prologue's barrier covers them)
     const bool edge_lane = (lane == nvalid - 1);
+    // clock codes carry each site's value before the flip (five bits, six to
+    // a register)
+    uint32_t old6[(RPW + 5) / 6];
+    if (kClock && kOut == kWriteCodes) {
+#pragma unroll
+        for (int k = 0; k < (RPW + 5) / 6; ++k) old6[k] = 0u;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) old6[r / 6] |= static_cast<uint32_t>(sreg[r]) << (5 * (r % 6));
+    }
 
     // Phase 1: decisions on the high bytes; ties go to the list.  The right
     // neighbour comes from the next lane by a DPP wave shift; the edge lane
@@ -472,20 +554,21 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t row = __umul24(y, L);
         const uint32_t i = row + static_cast<uint32_t>(xx);
         const Words4 lo = draw(i, t, kBondLo, k0, k1);
-        // (the fused kernel's spin buffer is being written by other
-        // workgroups, so its spins are recomputed from the previous forest)
-        auto spin_at = [&](uint32_t j) -> int {
-            if (kFused) return flipped<kClock>(root_word_of(a.labels_prev, j, a.ctl), kClock ? a.spins_prev[j] : 0, m_prev, q);
-            return a.spins[j];
+        // (the fused kernel has no spin array: its spins come from the
+        // previous codes)
+        auto spin_at = [&](int yy, int xc) -> int {
+            const uint32_t j2 = __umul24(yy, L) + static_cast<uint32_t>(xc);
+            if (kFused) return site_from_code<kClock>(a, a.codes_prev[j2], yy, xc, m_prev);
+            return a.spins[j2];
         };
-        const int s = kClock ? spin_at(i) : 0;  // a Potts tie implies equal spins
+        const int s = kClock ? spin_at(y, xx) : 0;  // a Potts tie implies equal spins
         if (e & (1u << 12)) {
-            const int sr = kClock ? spin_at(row + static_cast<uint32_t>((xx + 1 == L) ? 0 : xx + 1)) : 0;
+            const int sr = kClock ? spin_at(y, (xx + 1 == L) ? 0 : xx + 1) : 0;
             const uint32_t c = kClock ? cut[s * q + sr] : c_eq;
             if ((lo.w0 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_r[ly], 1ull << lx);
         }
         if (e & (1u << 13)) {
-            const int sd = kClock ? spin_at(__umul24((y + 1 == L) ? 0 : y + 1, L) + static_cast<uint32_t>(xx)) : 0;
+            const int sd = kClock ? spin_at((y + 1 == L) ? 0 : y + 1, xx) : 0;
             const uint32_t c = kClock ? cut[s * q + sd] : c_eq;
             if ((lo.w1 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_d[ly], 1ull << lx);
         }
@@ -504,7 +587,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 a.bond_d[wi] = raw_d[ly];
         }
     }
-    if (kBondsOnly) return;  // the label-equivalence labelers start from the bonds alone
+    if (kOut == kWriteBonds) return;  // the label-equivalence labelers start from the bonds alone
     // Border record, bond masks (lane = row of the tile for the column masks).
     if (wave == kW - 1) {
         const bool rowok = kFull || lane < nrows;
@@ -614,15 +697,95 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             }
         }
     }
-    // From here on every wave reads only its own rows of P: a run's first
-    // site holds its root, any other site points at its run's first site.
-    __syncthreads();
+    __syncthreads();  // every run's first site holds its root
     uint32_t rootreg[RPW];
+    if (kOut == kWriteCodes) {
+        // A run's first site holds its root and a root holds itself, so any
+        // site's root is two loads away.
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
+            rootreg[r] = P[P[self] & (kLdsWalkCap - 1u)] & (kLdsWalkCap - 1u);
+        }
+        // Roots of the perimeter sites (edges as in the border record: right
+        // column, bottom row, left column, top row), one edge per wave.
+        const uint32_t e = threadIdx.x >> 6, pos = ulane;
+        const bool perim = threadIdx.x < 4 * kTileW && static_cast<int>(pos) < ((e & 1u) ? nvalid : nrows);
+        uint32_t proot = 0;
+        if (perim) {
+            const uint32_t col = (e == 0) ? static_cast<uint32_t>(nvalid - 1) : (e == 2) ? 0u : pos;
+            const uint32_t row = (e == 1) ? static_cast<uint32_t>(nrows - 1) : (e == 3) ? 0u : pos;
+            proot = P[P[row * kTileW + col] & (kLdsWalkCap - 1u)] & (kLdsWalkCap - 1u);
+        }
+        __syncthreads();  // every root is read: P now holds per-root records
+        // Every component that reaches the perimeter becomes a node: the
+        // first perimeter site to mark its root takes the next slot.
+        if (perim) {
+            const uint32_t old = atomicOr(&P[proot], kMarkPerimeter);
+            if (!(old & kMarkPerimeter)) P[proot] = kMarkPerimeter | atomicAdd(&sh.nslots, 1u);
+        }
+        __syncthreads();
+        if (perim) a.border_slots[tile * (4 * kTileW) + threadIdx.x] = static_cast<uint8_t>(P[proot] & 0xFFu);
+        if (threadIdx.x == 0) a.nslots[tile] = sh.nslots;
+        // Each wave lists the roots of its rows in the high halves of its rows'
+        // forest words; then one lane per root draws the cluster value (Sec. 3
+        // assigns a new value to every label index; here only roots draw).  A
+        // perimeter root's draw goes to its node, the others' to their record.
+        uint16_t* const P16 = reinterpret_cast<uint16_t*>(P);
+        const uint32_t list0 = static_cast<uint32_t>(ly_base * kTileW);
+        uint32_t nroots = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const bool ok = kFull || (col_ok && (y_base + r < L));
+            const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
+            const uint64_t rm = __ballot(ok && rootreg[r] == self);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(rm >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(rm), 0u));
+            if (__builtin_amdgcn_inverse_ballot_w64(rm)) P16[2 * (list0 + nroots + below) + 1] = static_cast<uint16_t>(self);
+            nroots += static_cast<uint32_t>(__popcll(rm));
+        }
+        __builtin_amdgcn_wave_barrier();  // the list is read by other lanes of this wave only
+        uint64_t* const nodes = a.nodes + tile * kSlotsPerTile;
+        for (uint32_t j = ulane; j < nroots; j += 64) {
+            const uint32_t root = P16[2 * (list0 + j) + 1] & (kLdsWalkCap - 1u);
+            const uint32_t gi = tile_base + __umul24(root >> 6, L) + (root & 63u);
+            const uint32_t w = draw(gi, t, kCluster, k0, k1).w0;
+            const uint32_t v = kClock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
+            const uint32_t rec = P[root];
+            if (rec & kMarkPerimeter)
+                nodes[rec & 0xFFu] = (static_cast<uint64_t>(gi) << 32) | kNodeRoot | v;
+            else
+                P16[2 * root] = static_cast<uint16_t>(v);
+        }
+        __syncthreads();
+        // Codes: the new value of an inner component's sites, or the slot of
+        // the node (and, clock, the old value) of a perimeter component's.
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int y = y_base + r;
+            if (!(kFull || (col_ok && y < L))) continue;
+            const uint32_t rec = P[rootreg[r]] & 0xFFFFu;
+            uint32_t code;
+            const int old = kClock ? static_cast<int>((old6[r / 6] >> (5 * (r % 6))) & 31u) : 0;
+            if (rec & kMarkPerimeter)
+                code = kCodeNode | (kClock ? static_cast<uint32_t>(old) << 8 : 0u) | (rec & 0xFFu);
+            else
+                code = kClock ? static_cast<uint32_t>(flipped<true>(rec, old, m_cur, q)) : rec;
+            const uint32_t rb = __umul24(y, L) + static_cast<uint32_t>(x0);
+            (a.codes + rb)[ulane] = static_cast<uint16_t>(code);
+            if (a.lroot) (a.lroot + rb)[ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
+        }
+        return;
+    }
+    // One-level labels: every wave reads only its own rows of P (a run's
+    // first site holds its root, any other site points at its run's first
+    // site), since a wave's rows of P hold its root list afterwards.
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
         const uint32_t p = P[self];
-        rootreg[r] = __builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1)) ? p : P[p];
+        rootreg[r] = (__builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1)) ? p : P[p]) &
+                     (kLdsWalkCap - 1u);
     }
     // Border record, edge roots (global site indices), from the registers of
     // the waves that own the rows: right column (edge 0) by the lane of the
@@ -682,13 +845,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
 }
 
-template <int kModel, bool kFused, bool kBondsOnly, int kW>
+template <int kModel, int kSrc, int kOut, int kW>
 __device__ __forceinline__ void bond_tile(const SweepArgs& a, const int tx, const int ty) {
     __shared__ BondShared sh;
     if ((tx + 1) * kTileW <= a.L && (ty + 1) * kTileH <= a.L)
-        bond_local_tile<kModel, kFused, true, kBondsOnly, kW>(a, tx, ty, sh);
+        bond_local_tile<kModel, kSrc, kOut, true, kW>(a, tx, ty, sh);
     else
-        bond_local_tile<kModel, kFused, false, kBondsOnly, kW>(a, tx, ty, sh);
+        bond_local_tile<kModel, kSrc, kOut, false, kW>(a, tx, ty, sh);
 }
 
 // Thread g of a launch over the bonds that cross every step-th tile border
@@ -871,6 +1034,220 @@ __device__ __forceinline__ void border_merge(const SweepArgs& a, const uint32_t 
         }
     }
     if (wave_first(b.active && ra != rb, ra, rb)) g_union_roots(a.labels, ra, wa, rb, wb, a.ctl);
+}
+
+// ---------------------------------------------------------------------------
+// Two-level labels: the unions across tile borders on the node forest.  A
+// bond that leaves a tile joins the nodes of its two end sites' components
+// (from the tiles' border records of slots); the bond-skipping rule is that
+// of the one-level records.  Nodes are linked by their keys (smallest site
+// indices): the root with the larger key goes under the other by a 64-bit
+// compare-and-swap on its root word, so every cluster's root is the node of
+// its smallest site, which carries the cluster's draw.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lo32(uint64_t w) { return static_cast<uint32_t>(w); }
+__device__ __forceinline__ uint32_t hi32(uint64_t w) { return static_cast<uint32_t>(w >> 32); }
+
+__device__ __forceinline__ uint64_t n_load(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of node x, whose word w the caller has loaded, through ordinary
+// (cached) loads with path halving: a visited non-root gets its grandparent
+// in its low half.  A word read as a non-root can no longer be a root, so the
+// halving stores never touch a word a compare-and-swap works on.  kCoherent:
+// loads see every swap made so far (used after a failed swap).
+template <bool kCoherent>
+__device__ __forceinline__ uint32_t n_find_from(uint64_t* nodes, uint32_t x, uint64_t w, uint64_t* word,
+                                                const SweepArgs& a) {
+    for (uint32_t k = 0; !(lo32(w) & kNodeRoot); ++k) {
+        if (k >= a.node_cap) {
+            record_fault(a.ctl, kFaultGlobal);
+            break;
+        }
+        const uint32_t p = min(lo32(w), a.node_cap - 1u);  // (clamped: a broken forest stays in bounds)
+        const uint64_t wp = kCoherent ? n_load(&nodes[p]) : nodes[p];
+        if (lo32(wp) & kNodeRoot) {
+            *word = wp;
+            return p;
+        }
+        reinterpret_cast<uint32_t*>(&nodes[x])[0] = lo32(wp);
+        x = min(lo32(wp), a.node_cap - 1u);
+        w = kCoherent ? n_load(&nodes[x]) : nodes[x];
+    }
+    *word = w;
+    return x;
+}
+
+// Join the clusters of roots a and b (root words wa and wb).
+__device__ void n_union_roots(uint64_t* nodes, uint32_t a, uint64_t wa, uint32_t b, uint64_t wb, const SweepArgs& args) {
+    for (uint32_t k = 0; a != b; ++k) {
+        if (k >= args.node_cap || !(lo32(wa) & lo32(wb) & kNodeRoot)) {  // a walk gave up: the forest is broken
+            record_fault(args.ctl, kFaultGlobal);
+            return;
+        }
+        if (hi32(wa) > hi32(wb)) {
+            uint32_t tn = a;
+            a = b;
+            b = tn;
+            const uint64_t tw = wa;
+            wa = wb;
+            wb = tw;
+        }
+        uint64_t expected = wb;
+        const uint64_t link = (wb & 0xFFFFFFFF00000000ull) | a;
+        if (__hip_atomic_compare_exchange_strong(&nodes[b], &expected, link, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        // the failed swap returned b's current word; a's first load is
+        // issued before b's walk goes on
+        const uint64_t wa0 = n_load(&nodes[a]);
+        b = n_find_from<true>(nodes, b, expected, &wb, args);
+        a = n_find_from<true>(nodes, a, wa0, &wa, args);
+    }
+}
+
+// Node-forest ends of the bond that leaves tile (tx, row y) to the right, or
+// tile (ty, column x) downwards.
+__device__ __forceinline__ BorderBond vertical_node_bond(const SweepArgs& a, int tx, int y) {
+    const int ty = y / kTileH, ly = y - ty * kTileH;
+    const int t = ty * a.tiles_x + tx;
+    const int tr = ty * a.tiles_x + ((tx + 1 == a.tiles_x) ? 0 : tx + 1);
+    const uint64_t* m = a.border_bonds + static_cast<size_t>(t) * kBorderMasks;
+    const uint64_t rr = m[kRightR], rd = m[kRightD];
+    const uint64_t ld = a.border_bonds[static_cast<size_t>(tr) * kBorderMasks + kLeftD];
+    const uint32_t si = a.border_slots[static_cast<size_t>(t) * (4 * kTileW) + 0 * kTileW + ly];
+    const uint32_t sj = a.border_slots[static_cast<size_t>(tr) * (4 * kTileW) + 2 * kTileW + ly];
+    const bool skip = ly != 0 && bit(rr, ly - 1) && bit(rd, ly - 1) && bit(ld, ly - 1);
+    return {bit(rr, ly) && !skip, static_cast<uint32_t>(t) * kSlotsPerTile + si,
+            static_cast<uint32_t>(tr) * kSlotsPerTile + sj};
+}
+
+__device__ __forceinline__ BorderBond horizontal_node_bond(const SweepArgs& a, int ty, int x) {
+    const int tx = x / kTileW, lx = x - tx * kTileW;
+    const int t = ty * a.tiles_x + tx;
+    const int td = ((ty + 1 == a.tiles_y) ? 0 : ty + 1) * a.tiles_x + tx;
+    const uint64_t* m = a.border_bonds + static_cast<size_t>(t) * kBorderMasks;
+    const uint64_t bd = m[kBottomD], br = m[kBottomR];
+    const uint64_t tr = a.border_bonds[static_cast<size_t>(td) * kBorderMasks + kTopR];
+    const uint32_t si = a.border_slots[static_cast<size_t>(t) * (4 * kTileW) + 1 * kTileW + lx];
+    const uint32_t sj = a.border_slots[static_cast<size_t>(td) * (4 * kTileW) + 3 * kTileW + lx];
+    const bool skip = lx != 0 && bit(bd, lx - 1) && bit(br, lx - 1) && bit(tr, lx - 1);
+    return {bit(bd, lx) && !skip, static_cast<uint32_t>(t) * kSlotsPerTile + si,
+            static_cast<uint32_t>(td) * kSlotsPerTile + sj};
+}
+
+// Thread g: row g % L of vertical border g / L (every tile column's right
+// edge), then column h % L of horizontal border h / L.
+__device__ __forceinline__ void node_merge(const SweepArgs& a, uint32_t g) {
+    if (!a.ctl->live) return;
+    // every kernel that reads this sweep's index has run (stream order)
+    if (g == 0) a.ctl->t += 1;
+    const uint32_t L = static_cast<uint32_t>(a.L);
+    const uint32_t nv = static_cast<uint32_t>(a.tiles_x) * L, nh = static_cast<uint32_t>(a.tiles_y) * L;
+    BorderBond b = {false, 0u, 0u};
+    if (g < nv) {
+        const uint32_t k = g / L;
+        b = vertical_node_bond(a, static_cast<int>(k), static_cast<int>(g - k * L));
+    } else if (g - nv < nh) {
+        const uint32_t h = g - nv, k = h / L;
+        b = horizontal_node_bond(a, static_cast<int>(k), static_cast<int>(h - k * L));
+    }
+    uint32_t ra = 0, rb = 0;
+    uint64_t wa = 0, wb = 0;
+    if (b.active) {
+        // the two first loads are issued together; most walks end there
+        const uint64_t wi = a.nodes[b.i], wj = a.nodes[b.j];
+        ra = n_find_from<false>(a.nodes, b.i, wi, &wa, a);
+        rb = n_find_from<false>(a.nodes, b.j, wj, &wb, a);
+        if (ra > rb) {
+            const uint32_t tn = ra;
+            ra = rb;
+            rb = tn;
+            const uint64_t tw = wa;
+            wa = wb;
+            wb = tw;
+        }
+    }
+    if (wave_first(b.active && ra != rb, ra, rb)) n_union_roots(a.nodes, ra, wa, rb, wb, a);
+}
+
+// The last sweep's flip from its codes and merged node forest: one tile per
+// workgroup, the tile's node draws (and keys) resolved once into LDS, then
+// sixteen consecutive sites of a row per thread.  With kVerify the canonical
+// labels follow: the tile-local root of an inner component's sites, the key
+// of the cluster root for a perimeter component's.
+template <bool kVerify>
+__device__ __forceinline__ void code_flip(const SweepArgs& a, const int tx, const int ty) {
+    __shared__ uint32_t val[kSlotsPerTile];
+    __shared__ uint32_t key[kSlotsPerTile];
+    if (!a.ctl->live) return;
+    const int L = a.L;
+    const uint32_t tile = static_cast<uint32_t>(ty * a.tiles_x + tx);
+    const uint32_t ns = min(a.nslots[tile], kSlotsPerTile);
+    for (uint32_t k = threadIdx.x; k < ns; k += blockDim.x) {
+        const uint32_t n = tile * kSlotsPerTile + k;
+        uint64_t w = a.nodes[n];
+        for (uint32_t s = 0; !(lo32(w) & kNodeRoot); ++s) {
+            if (s >= a.node_cap) {
+                record_fault(a.ctl, kFaultFlip);
+                w = kNodeRoot;
+                break;
+            }
+            w = a.nodes[min(lo32(w), a.node_cap - 1u)];
+        }
+        val[k] = lo32(w) & 0xFFu;
+        key[k] = hi32(w);
+    }
+    __syncthreads();
+    const int ly = static_cast<int>(threadIdx.x >> 2), lx = static_cast<int>(threadIdx.x & 3) * 16;
+    const int y = ty * kTileH + ly;
+    const int xs = tx * kTileW + lx;
+    const int nx = (y < L) ? max(0, min(16, L - xs)) : 0;
+    if (nx == 0) return;
+    const uint32_t base = __umul24(y, L) + static_cast<uint32_t>(xs);
+    const int m = static_cast<int>(a.ctl->mirror);
+    const bool full = (nx == 16) && ((base & 15u) == 0);
+    uint32_t c[16];
+    if (full) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const uint4 v = *reinterpret_cast<const uint4*>(a.codes + base + 8 * g);
+            c[8 * g] = v.x & 0xFFFFu; c[8 * g + 1] = v.x >> 16;
+            c[8 * g + 2] = v.y & 0xFFFFu; c[8 * g + 3] = v.y >> 16;
+            c[8 * g + 4] = v.z & 0xFFFFu; c[8 * g + 5] = v.z >> 16;
+            c[8 * g + 6] = v.w & 0xFFFFu; c[8 * g + 7] = v.w >> 16;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c[k] = (k < nx) ? a.codes[base + k] : 0u;
+    }
+    uint32_t out[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t ck = c[k];
+        uint32_t v = ck & 31u;
+        if (ck & kCodeNode) {
+            const uint32_t d = val[ck & 0xFFu];
+            v = (a.model == 1) ? static_cast<uint32_t>(flipped<true>(d, static_cast<int>((ck >> 8) & 31u), m, a.q)) : d;
+        }
+        out[k] = v;
+    }
+    if (full) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            *reinterpret_cast<uint32_t*>(a.flip_out + base + 4 * g) =
+                out[4 * g] | (out[4 * g + 1] << 8) | (out[4 * g + 2] << 16) | (out[4 * g + 3] << 24);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < nx) a.flip_out[base + k] = static_cast<int8_t>(out[k]);
+    }
+    if (kVerify) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < nx) a.canon[base + k] = (c[k] & kCodeNode) ? key[c[k] & 0xFFu] : a.lroot[base + k];
+    }
 }
 
 // After the merge: every tile-local root at the end of a border bond that
@@ -1433,6 +1810,39 @@ __device__ __forceinline__ void hash_sum(const uint64_t* part, uint32_t nblocks,
     }
 }
 
+// Per-sweep hashes from the codes, the tile-local roots and the merged node
+// forest (before the next sweep overwrites them): the new state and the
+// canonical labels, as hash_sweep computes them from a one-level forest.
+__device__ __forceinline__ void code_hash(const SweepArgs& a, uint32_t block, uint32_t nblocks) {
+    if (!a.ctl->live) return;
+    const uint32_t N = __umul24(a.L, a.L);
+    const int m = a.model == 1 ? static_cast<int>(a.ctl->mirror) : 0;
+    uint64_t hs = 0, hl = 0;
+    for (uint32_t i = block * kHashThreads + threadIdx.x; i < N; i += nblocks * kHashThreads) {
+        const uint32_t ck = a.codes[i];
+        uint32_t v = ck & 31u, lab = a.lroot[i];
+        if (ck & kCodeNode) {
+            const uint32_t y = i / static_cast<uint32_t>(a.L), xx = i - y * static_cast<uint32_t>(a.L);
+            const uint32_t tile = (y >> 6) * static_cast<uint32_t>(a.tiles_x) + (xx >> 6);
+            uint64_t w = a.nodes[tile * kSlotsPerTile + (ck & 0xFFu)];
+            for (uint32_t s = 0; !(lo32(w) & kNodeRoot); ++s) {
+                if (s >= a.node_cap) {
+                    record_fault(a.ctl, kFaultHash);
+                    w = kNodeRoot;
+                    break;
+                }
+                w = a.nodes[min(lo32(w), a.node_cap - 1u)];
+            }
+            const uint32_t d = lo32(w) & 0xFFu;
+            v = (a.model == 1) ? static_cast<uint32_t>(flipped<true>(d, static_cast<int>((ck >> 8) & 31u), m, a.q)) : d;
+            lab = hi32(w);
+        }
+        hs += mix64((static_cast<uint64_t>(i) << 8) | static_cast<uint8_t>(v));
+        hl += mix64((static_cast<uint64_t>(i) << 32) | lab);
+    }
+    hash_store_partial(hs, hl, a.hash_partial + 2 * static_cast<size_t>(block));
+}
+
 __global__ void __launch_bounds__(kHashThreads) k_hash_sweep(SweepArgs a) { hash_sweep(a, blockIdx.x, gridDim.x); }
 
 __global__ void __launch_bounds__(kHashThreads) k_hash_sum(SweepArgs a, uint32_t row) {
@@ -1474,7 +1884,7 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
 template <int kModel, int kW>
 __global__ void __launch_bounds__(kW * 64) k_bond_local(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<kModel, false, false, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<kModel, kFromSpins, kWriteLabels, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 // Eight waves per SIMD (the scalar registers over the limit spill to vector
@@ -1482,19 +1892,25 @@ __global__ void __launch_bounds__(kW * 64) k_bond_local(SweepArgs a) {
 template <int kModel>
 __global__ void __launch_bounds__(kBlock) k_bonds_only(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<kModel, false, true, kWaves>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<kModel, kFromSpins, kWriteBonds, kWaves>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-template <int kW>
-__global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_potts(SweepArgs a) {
+// Single lattices: the bond kernel with two-level labels, from the spins
+// (a call's first sweep) or from the previous sweep's codes and node forest.
+// Eight waves per SIMD (the scalar registers over the limit spill to vector
+// lanes).
+template <int kSrc, int kW>
+__global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) k_code_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<0, true, false, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<0, kSrc, kWriteCodes, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-template <int kW>
-__global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) k_flip_bond_clock(SweepArgs a) {
+// The clock model's kernel keeps each site's old value through the labeling
+// and does not fit 64 registers without scratch: seven waves per SIMD.
+template <int kSrc, int kW>
+__global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(7, 7))) k_code_bond_clock(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
-    bond_tile<1, true, false, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+    bond_tile<1, kSrc, kWriteCodes, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { block_merge(a, blockIdx.x, blockIdx.y); }
@@ -1529,6 +1945,18 @@ __global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
 }
 
 __global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, border_block(a, 1)); }
+
+__global__ void __launch_bounds__(256) k_node_merge(SweepArgs a) {
+    node_merge(a, border_block(a, 1) * blockDim.x + threadIdx.x);
+}
+
+template <bool kVerify>
+__global__ void __launch_bounds__(256) k_code_flip(SweepArgs a) {
+    const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    code_flip<kVerify>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
+}
+
+__global__ void __launch_bounds__(kHashThreads) k_code_hash(SweepArgs a) { code_hash(a, blockIdx.x, gridDim.x); }
 
 template <bool kVerify>
 __global__ void __launch_bounds__(256) k_flip(SweepArgs a) {
@@ -1661,7 +2089,7 @@ template <int kModel>
 __global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    bond_tile<kModel, false, false, kWaves>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+    bond_tile<kModel, kFromSpins, kWriteLabels, kWaves>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
@@ -1727,14 +2155,10 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t s) {
 }
 
 template <int kW>
-static void launch_bond_tiles(const SweepArgs& a, bool fused, hipStream_t s) {
+static void launch_bond_tiles(const SweepArgs& a, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
     const dim3 block(kW * 64);
-    if (fused && a.model == 1)
-        hipLaunchKernelGGL(k_flip_bond_clock<kW>, grid, block, cut_bytes(a.q), s, a);
-    else if (fused)
-        hipLaunchKernelGGL(k_flip_bond_potts<kW>, grid, block, 0, s, a);
-    else if (a.model == 1)
+    if (a.model == 1)
         hipLaunchKernelGGL((k_bond_local<1, kW>), grid, block, cut_bytes(a.q), s, a);
     else
         hipLaunchKernelGGL((k_bond_local<0, kW>), grid, block, 0, s, a);
@@ -1742,17 +2166,52 @@ static void launch_bond_tiles(const SweepArgs& a, bool fused, hipStream_t s) {
 
 hipError_t launch_bond_local(const SweepArgs& a, hipStream_t s) {
     if (a.tile_waves == kWavesSmall)
-        launch_bond_tiles<kWavesSmall>(a, false, s);
+        launch_bond_tiles<kWavesSmall>(a, s);
     else
-        launch_bond_tiles<kWaves>(a, false, s);
+        launch_bond_tiles<kWaves>(a, s);
     return hipGetLastError();
 }
 
-hipError_t launch_flip_bond(const SweepArgs& a, hipStream_t s) {
-    if (a.tile_waves == kWavesSmall)
-        launch_bond_tiles<kWavesSmall>(a, true, s);
+template <int kW>
+static void launch_code_tiles(const SweepArgs& a, bool fused, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
+    const dim3 block(kW * 64);
+    if (a.model == 1 && fused)
+        hipLaunchKernelGGL((k_code_bond_clock<kFromCodes, kW>), grid, block, cut_bytes(a.q), s, a);
+    else if (a.model == 1)
+        hipLaunchKernelGGL((k_code_bond_clock<kFromSpins, kW>), grid, block, cut_bytes(a.q), s, a);
+    else if (fused)
+        hipLaunchKernelGGL((k_code_bond_potts<kFromCodes, kW>), grid, block, 0, s, a);
     else
-        launch_bond_tiles<kWaves>(a, true, s);
+        hipLaunchKernelGGL((k_code_bond_potts<kFromSpins, kW>), grid, block, 0, s, a);
+}
+
+hipError_t launch_code_bond(const SweepArgs& a, bool fused, hipStream_t s) {
+    if (a.tile_waves == kWavesSmall)
+        launch_code_tiles<kWavesSmall>(a, fused, s);
+    else
+        launch_code_tiles<kWaves>(a, fused, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_merge(const SweepArgs& a, hipStream_t s) {
+    const size_t n = (static_cast<size_t>(a.tiles_x) + a.tiles_y) * a.L;
+    hipLaunchKernelGGL(k_node_merge, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_code_flip(const SweepArgs& a, bool verify, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y));
+    if (verify)
+        hipLaunchKernelGGL(k_code_flip<true>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_code_flip<false>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_code_hash(const SweepArgs& a, uint32_t row, hipStream_t s) {
+    hipLaunchKernelGGL(k_code_hash, dim3(hash_blocks(a.L)), dim3(kHashThreads), 0, s, a);
+    hipLaunchKernelGGL(k_hash_sum, dim3(1), dim3(kHashThreads), 0, s, a, row);
     return hipGetLastError();
 }
 

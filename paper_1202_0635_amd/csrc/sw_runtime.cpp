@@ -126,7 +126,7 @@ extern "C" {
 
 size_t sw_state_bytes(const sw_lattice* p) {
     std::string why;
-    if (!lattice_ok(p, &why)) {
+    if (!lattice_ok(p, &why, kMaxSide)) {
         fail(SW_EINVAL, "%s", why.c_str());
         return 0;
     }
@@ -135,7 +135,7 @@ size_t sw_state_bytes(const sw_lattice* p) {
 
 int sw_cutoff_table(const sw_lattice* p, uint32_t* out, size_t n) {
     std::string why;
-    if (!lattice_ok(p, &why)) return fail(SW_EINVAL, "%s", why.c_str());
+    if (!lattice_ok(p, &why, kMaxSide)) return fail(SW_EINVAL, "%s", why.c_str());
     if (!out || n != table_entries(*p)) return fail(SW_EINVAL, "table size must be %zu", table_entries(*p));
     build_table(*p, out);
     return SW_OK;
@@ -145,7 +145,7 @@ int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_c
     if (!out) return fail(SW_EINVAL, "null output pointer");
     *out = nullptr;
     std::string why;
-    if (!lattice_ok(p, &why)) return fail(SW_EINVAL, "%s", why.c_str());
+    if (!lattice_ok(p, &why, kMaxSide)) return fail(SW_EINVAL, "%s", why.c_str());
     const Layout lay = layout_of(*p, true);
     if (dev_mem) {
         if (reinterpret_cast<uintptr_t>(dev_mem) % kAlign != 0) return fail(SW_EINVAL, "dev_mem must be 256-byte aligned");
@@ -256,13 +256,10 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         rows = 0;
         return st2;
     };
-    // Sweeps after the first of a call fuse the previous sweep's flip into
-    // their bond kernel: spins and labels alternate between the context's two
-    // buffers, and the call ends with a flip into the primary spin buffer.
+    // The primary spin buffer and the second one that measured sweeps
+    // alternate with.
     int8_t* const spins0 = c->args.spins;
     int8_t* const spins1 = reinterpret_cast<int8_t*>(c->base + c->lay.spins2);
-    uint32_t* const labels0 = c->args.labels;
-    uint32_t* const labels1 = reinterpret_cast<uint32_t*>(c->base + c->lay.labels2);
     // Union-find path with measurement (not profiled): the count of a state
     // runs on the side stream after the kernel that wrote the state, and the
     // next kernel that overwrites that spin buffer (two sweeps later, or the
@@ -299,7 +296,10 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         // The paper's labelers: every sweep is bonds, label equivalence until
         // a scan changes nothing, root words, flip.
         SweepArgs a = c->args;
-        uint32_t* R = (c->labeler == kHawick) ? reinterpret_cast<uint32_t*>(c->base + c->lay.labels2) : nullptr;
+        // Hawick et al.'s temporary array lives in the canonical-label buffer,
+        // which the flip of a verified sweep fills only after the labeling
+        uint32_t* R = (c->labeler == kHawick) ? c->args.canon : nullptr;
+        if (R) c->have_canon = false;
         uint32_t* changed = &a.ctl->changed;
         const int64_t cap = 4ll * c->p.L + 64;  // labels fall at every pass that continues
         for (int32_t s = 0; s < nsweeps; ++s) {
@@ -341,53 +341,74 @@ int sw_sweep(sw_ctx* c, int32_t nsweeps, uint32_t flags) {
         if (st) return st;
         return flush_ring(c, rows);
     }
+    // Union-find with two-level labels.  The first sweep of a call reads the
+    // spins; every later one reads the previous sweep's codes and node forest
+    // (the flip of that sweep, fused into the bond kernel), so codes, node
+    // forests and node counts alternate between two buffers.  The merge joins
+    // the node forest across tile borders; the call ends with the flip of its
+    // last sweep into the primary spin buffer.  Measured sweeps have their
+    // state stored by the fused kernel, alternately in the two spin buffers.
+    uint16_t* const codes[2] = {reinterpret_cast<uint16_t*>(c->base + c->lay.codes[0]),
+                                reinterpret_cast<uint16_t*>(c->base + c->lay.codes[1])};
+    uint64_t* const nodes[2] = {reinterpret_cast<uint64_t*>(c->base + c->lay.nodes[0]),
+                                reinterpret_cast<uint64_t*>(c->base + c->lay.nodes[1])};
+    uint32_t* const nslots[2] = {reinterpret_cast<uint32_t*>(c->base + c->lay.nslots[0]),
+                                 reinterpret_cast<uint32_t*>(c->base + c->lay.nslots[1])};
     SweepArgs a = c->args;
+    a.border_slots = reinterpret_cast<uint8_t*>(c->base + c->lay.border_slots);
     for (int32_t s = 0; s < nsweeps; ++s) {
         const bool last = s == nsweeps - 1;
         const bool verify = (flags & SW_VERIFY) && last;
+        const int b = s & 1;
+        SweepArgs f = a;
+        f.codes = codes[b];
+        f.nodes = nodes[b];
+        f.nslots = nslots[b];
+        f.lroot = (hash || verify) ? c->args.labels : nullptr;  // tile-local roots, for canonical labels
+        f.spins_out = nullptr;
         if (s == 0) {
-            st = timed(c, profile, kKBondLocal, [&] { return launch_bond_local(a, c->stream); });
+            f.spins = spins0;
+            st = timed(c, profile, kKCodeBond, [&] { return launch_code_bond(f, false, c->stream); });
             if (st) return st;
         } else {
-            SweepArgs f = a;
-            f.labels_prev = a.labels;
-            f.spins_prev = a.spins;
-            f.labels = (a.labels == labels0) ? labels1 : labels0;
-            f.spins = (a.spins == spins0) ? spins1 : spins0;
-            st = before_write(f.spins);
+            f.codes_prev = codes[b ^ 1];
+            f.nodes_prev = nodes[b ^ 1];
+            f.nslots_prev = nslots[b ^ 1];
+            if (measure) {
+                f.spins_out = b ? spins1 : spins0;
+                st = before_write(f.spins_out);
+                if (st) return st;
+            }
+            st = timed(c, profile, kKCodeFlipBond, [&] { return launch_code_bond(f, true, c->stream); });
             if (st) return st;
-            st = timed(c, profile, kKFlipBond, [&] { return launch_flip_bond(f, c->stream); });
-            if (st) return st;
-            a = f;
-            if (measure) {  // the state after sweep s - 1, which the fused kernel wrote
-                st = count_state(a);
+            if (measure) {  // the state after sweep s - 1, which the fused kernel stored
+                SweepArgs m = f;
+                m.spins = f.spins_out;
+                st = count_state(m);
                 if (st) return st;
             }
         }
-        if (a.merge_tiles > 1) {
-            st = timed(c, profile, kKBlockMerge, [&] { return launch_block_merge(a, c->stream); });
+        st = timed(c, profile, kKNodeMerge, [&] { return launch_node_merge(f, c->stream); });
+        if (st) return st;
+        if (hash) {
+            st = timed(c, profile, kKHash, [&] { return launch_code_hash(f, static_cast<uint32_t>(hrows), c->stream); });
             if (st) return st;
+            if (++hrows == kRing) {
+                st = flush_hashes();
+                if (st) return st;
+            }
         }
-        st = timed(c, profile, kKBorderMerge, [&] { return launch_border_merge(a, c->stream); });
-        if (st) return st;
-        st = hash_sweep(a);
-        if (st) return st;
-        // a verified sweep's canonical labels need the links; otherwise the
-        // flatten leaves root words where the next flip looks
-        a.root_copies = verify ? 0 : 1;
-        st = timed(c, profile, kKFlatten, [&] { return launch_flatten(a, c->stream); });
-        if (st) return st;
         if (last) {
-            SweepArgs f = a;
-            f.flip_out = spins0;
+            SweepArgs g = f;
+            g.flip_out = spins0;
             st = before_write(spins0);
             if (st) return st;
-            st = timed(c, profile, kKFlip, [&] { return launch_flip(f, verify, c->stream); });
+            st = timed(c, profile, kKCodeFlip, [&] { return launch_code_flip(g, verify, c->stream); });
             if (st) return st;
             if (verify) c->have_canon = true;
             if (measure) {
-                f.spins = spins0;
-                st = count_state(f);
+                g.spins = spins0;
+                st = count_state(g);
                 if (st) return st;
             }
         }
@@ -543,6 +564,8 @@ int sw_set_labeler(sw_ctx* c, int32_t labeler) {
     if (st) return st;
     if (labeler != SW_LABEL_UNION_FIND && labeler != SW_LABEL_HAWICK && labeler != SW_LABEL_KALENTEV)
         return fail(SW_EINVAL, "labeler must be SW_LABEL_UNION_FIND, SW_LABEL_HAWICK or SW_LABEL_KALENTEV");
+    if (labeler != SW_LABEL_UNION_FIND && c->p.L > kMaxSideFlagged)
+        return fail(SW_EINVAL, "the label-equivalence labelers take L <= %d", kMaxSideFlagged);
     c->labeler = labeler;
     return SW_OK;
 }
@@ -564,19 +587,10 @@ int sw_set_tile_waves(sw_ctx* c, int32_t waves) {
     return SW_OK;
 }
 
-int sw_set_schedule(sw_ctx* c, int32_t merge_tiles) {
-    const int st = check_ctx(c);
-    if (st) return st;
-    if (merge_tiles != 1 && merge_tiles != 2 && merge_tiles != 4)
-        return fail(SW_EINVAL, "merge_tiles must be 1, 2 or 4");
-    c->args.merge_tiles = merge_tiles;
-    return SW_OK;
-}
-
-int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles) {
+int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* waves) {
     int st = check_ctx(c);
     if (st) return st;
-    if (sweeps <= 0 || !merge_tiles) return fail(SW_EINVAL, "need sweeps > 0 and an output pointer");
+    if (sweeps <= 0 || !waves) return fail(SW_EINVAL, "need sweeps > 0 and an output pointer");
     const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
     void* tmp = nullptr;
     SW_HIP(c, hipMalloc(&tmp, up(N) + up(sizeof(Control))));
@@ -589,15 +603,14 @@ int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // Three rounds, each timing every schedule from the same saved state; a
-    // schedule's time is its fastest round (the schedules' times differ by a
-    // few per cent, about as much as one timing varies).
-    const int kSchedules[3] = {1, 2, 4};
-    float best_of[3] = {0.0f, 0.0f, 0.0f};
+    // Three rounds, each timing every choice from the same saved state; a
+    // choice's time is its fastest round.
+    const int kChoices[2] = {kWaves, kWavesSmall};
+    float best_of[2] = {0.0f, 0.0f};
     for (int round = 0; round < 3; ++round) {
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 2; ++k) {
             if (e != hipSuccess || st) break;
-            c->args.merge_tiles = kSchedules[k];
+            c->args.tile_waves = kChoices[k];
             st = sw_sweep(c, 1, 0);
             if (!st) e = hipEventRecord(e0, c->stream);
             if (!st && e == hipSuccess) st = sw_sweep(c, sweeps, 0);
@@ -610,12 +623,12 @@ int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles) {
             if (!st && e == hipSuccess) e = hipMemcpyAsync(ctl, s_ctl, sizeof(Control), hipMemcpyDeviceToDevice, c->stream);
         }
     }
-    int best = c->args.merge_tiles;
+    int best = c->args.tile_waves;
     float best_ms = 0.0f;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
         if (best_of[k] > 0.0f && (best_ms == 0.0f || best_of[k] < best_ms)) {
             best_ms = best_of[k];
-            best = kSchedules[k];
+            best = kChoices[k];
         }
     if (e == hipSuccess && !st) e = hipStreamSynchronize(c->stream);
     if (e0) (void)hipEventDestroy(e0);
@@ -623,9 +636,9 @@ int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* merge_tiles) {
     (void)hipFree(tmp);
     if (st) return st;
     if (e != hipSuccess) return device_fail(c, e, "sw_tune");
-    c->args.merge_tiles = best;
+    c->args.tile_waves = best;
     c->have_canon = false;
-    *merge_tiles = best;
+    *waves = best;
     return SW_OK;
 }
 

@@ -54,6 +54,17 @@ static void test_params() {
         b.L = L;
         CHECK(!lattice_ok(&b, &why));
     }
+    // single lattices (two-level labels) go up to 65535
+    for (int L : {46341, 65535}) {
+        sw_lattice b = p;
+        b.L = L;
+        CHECK(lattice_ok(&b, &why, kMaxSide));
+    }
+    {
+        sw_lattice b = p;
+        b.L = 65536;
+        CHECK(!lattice_ok(&b, &why, kMaxSide));
+    }
     for (int q : {1, 33}) {
         sw_lattice b = p;
         b.q = q;
@@ -106,7 +117,7 @@ static void test_tables() {
 }
 
 static void test_layout() {
-    for (int L : {2, 3, 63, 64, 65, 100, 1030, 4096}) {
+    for (int L : {2, 3, 63, 64, 65, 100, 1030, 4096, 65535}) {
         for (bool pair : {false, true}) {
             sw_lattice p = lat(L, 6, SW_CLOCK, 0.9);
             const Layout l = layout_of(p, pair);
@@ -118,8 +129,14 @@ static void test_layout() {
                 {l.hash_ring, static_cast<size_t>(kRing) * 16}, {l.hash_partial, kHashPartWords * 8},
                 {l.table, table_entries(p) * 4}};
             if (pair) {
+                const size_t tiles = static_cast<size_t>((L + kTileW - 1) / kTileW) * ((L + kTileH - 1) / kTileH);
                 r.push_back({l.spins2, N});
-                r.push_back({l.labels2, N * 4});
+                for (int b = 0; b < 2; ++b) {
+                    r.push_back({l.codes[b], N * 2});
+                    r.push_back({l.nodes[b], tiles * kSlotsPerTile * 8});
+                    r.push_back({l.nslots[b], tiles * 4});
+                }
+                r.push_back({l.border_slots, tiles * 4 * kTileW});
             }
             for (auto& a : r) {
                 CHECK(a.first % kAlign == 0);

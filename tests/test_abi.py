@@ -65,7 +65,7 @@ def test_state_bytes_and_invalid_parameters(swlib):
     n = lib.sw_state_bytes(ctypes.byref(good))
     assert n >= 4096 * 4096 * (1 + 4 + 4) and n % 256 == 0
     bad = [
-        _lattice(swlib, 1, 2, 0, 1.0), _lattice(swlib, 46341, 2, 0, 1.0), _lattice(swlib, 16, 1, 0, 1.0),
+        _lattice(swlib, 1, 2, 0, 1.0), _lattice(swlib, 65536, 2, 0, 1.0), _lattice(swlib, 16, 1, 0, 1.0),
         _lattice(swlib, 16, 33, 0, 1.0), _lattice(swlib, 16, 2, 2, 1.0), _lattice(swlib, 16, 2, 0, 0.0),
         _lattice(swlib, 16, 2, 0, -1.0), _lattice(swlib, 16, 2, 0, math.inf), _lattice(swlib, 16, 2, 0, 1.0, J=0.0),
         _lattice(swlib, 16, 2, 0, 1.0, reserved=1),
@@ -109,3 +109,16 @@ def test_static_entry_rejects_before_device_work(swlib):
     bad = _lattice(swlib, 64, 1, 0, 1.0)
     assert lib.sw_sweep_static(ctypes.byref(bad), dummy, 0, 1, dummy, None, None, None) == swlib.SW_EINVAL
     assert lib.sw_sweep_static(ctypes.byref(ok), ctypes.c_void_p(0x1001), 0, 1, dummy, None, None, None) == swlib.SW_EINVAL
+
+
+def test_side_limits(swlib):
+    """Single lattices take L up to 65535 (two-level labels); batches and the
+    static entry point keep one-level label words and stop at 46340."""
+    lib = swlib.lib()
+    wide = _lattice(swlib, 65535, 2, 0, 1.0)
+    assert lib.sw_state_bytes(ctypes.byref(wide)) > 65535 * 65535 * 4
+    over = _lattice(swlib, 46341, 2, 0, 1.0)
+    assert lib.sw_state_bytes(ctypes.byref(over)) > 0
+    assert lib.sw_batch_bytes(ctypes.byref(over), 1) == 0
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.sw_sweep_static(ctypes.byref(over), dummy, 0, 1, dummy, None, None, None) == swlib.SW_EINVAL

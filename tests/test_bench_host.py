@@ -36,9 +36,11 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_fused_kernel_bytes_per_site():
-    # 9.375 B per site for the Potts fused kernel (labels of the previous sweep
-    # with the halo, old and new spins, bond bits, new labels); the clock model
-    # adds the old spins of the mirror test, with their halo
+    # the fused kernel does the work of the flip (labels read, spins written;
+    # the clock model also reads the old spins) and of the bond kernel (spins
+    # and the halo read, bond bits and labels written): 5 + 5.28125 B per site
     L = 4096
-    assert bench.alg_bytes_per_launch("k_flip_bond", L, "potts") == pytest.approx(9.375 * L * L)
-    assert bench.alg_bytes_per_launch("k_flip_bond", L, "clock") == pytest.approx((9.375 + 1 + 1 / 32) * L * L)
+    assert bench.alg_bytes_per_launch("k_code_flip_bond", L, "potts") == pytest.approx(10.28125 * L * L)
+    assert bench.alg_bytes_per_launch("k_code_flip_bond", L, "clock") == pytest.approx(11.28125 * L * L)
+    # the merge: per tile-border site one bond bit and two label words
+    assert bench.alg_bytes_per_launch("k_node_merge", L, "potts") == pytest.approx(L * 128 * 8.125)

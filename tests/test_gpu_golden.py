@@ -66,16 +66,16 @@ def _chunks(total, pattern):
 
 
 # Ising L = 64 at T_c, all 1000 sweeps: single-sweep calls and fused calls of
-# varying length, under every merge schedule and both tile shapes.
+# varying length, with both tile shapes.
 @pytest.mark.parametrize("pattern", [(1,), (1, 2, 3, 5, 8, 13, 21, 34, 55, 89), (1000,), (7, 250, 1, 64)])
-@pytest.mark.parametrize("mt,waves", [(1, 4), (4, 4), (2, 8), (1, 8)])
-def test_ising_L64_every_sweep(swmc, pattern, mt, waves):
+@pytest.mark.parametrize("waves", [4, 8])
+def test_ising_L64_every_sweep(swmc, pattern, waves):
     from paper_1202_0635_amd.workloads import ISING_L64 as c
 
     gold = chain_golden(c.name)
     calls = _chunks(c.sweeps, pattern)
-    _say(f"[golden C1] schedule={mt} waves={waves} calls={len(calls)}")
-    lat = swmc.Lattice(c.L, c.q, c.model, T=c.T, J=c.J, seed=c.seed).set_schedule(mt).set_tile_waves(waves)
+    _say(f"[golden C1] waves={waves} calls={len(calls)}")
+    lat = swmc.Lattice(c.L, c.q, c.model, T=c.T, J=c.J, seed=c.seed).set_tile_waves(waves)
     for n in calls:
         lat.sweep(n, hash=True)
     got = lat.hashes()
@@ -88,7 +88,7 @@ def test_ising_L64_every_sweep(swmc, pattern, mt, waves):
 
 # The two L = 4096 workloads through their 200 thermalisation sweeps and 50
 # more, in the benchmark's multi-sweep calls (fused flip-and-bond kernel) and
-# with the autotuner's schedule.
+# with the autotuner's choice of waves per tile.
 @pytest.mark.parametrize("name", ["potts2_L4096_Tc", "clock6_L4096_T0.9"])
 @pytest.mark.parametrize("pattern", [(250,), (1, 1, 3, 45, 150, 50)])
 def test_L4096_thermalisation(swmc, name, pattern):
@@ -102,7 +102,7 @@ def test_L4096_thermalisation(swmc, name, pattern):
     lat = swmc.Lattice(c.L, c.q, c.model, T=c.T, J=c.J, seed=c.seed)
     if pattern == (250,):
         lat.sweep(5, hash=True)
-        lat.tune(3)  # times each schedule from this state and restores it
+        lat.tune(3)  # times each choice from this state and restores it
         calls = _chunks(n_gold - 5, pattern)
     for n in calls:
         lat.sweep(n, hash=True)

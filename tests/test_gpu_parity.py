@@ -87,18 +87,19 @@ def test_parity_from_arbitrary_state(swmc, orc, L, q, model, T):
 
 
 # Several sweeps in one call run the previous sweep's flip inside the next
-# sweep's bond kernel (alternating spin and label buffers); the state after
-# every call, and the last sweep's labels, must be the oracle's.
+# sweep's bond kernel (from the previous sweep's codes and node forest,
+# alternating between two buffers); the state after every call, and the last
+# sweep's bonds and labels, must be the oracle's.
 @pytest.mark.parametrize("L,q,model,T,seed,calls", [
     (2, 2, "potts", TC2, 5, (4, 3)), (3, 3, "potts", 0.7, 9, (5,)), (5, 6, "clock", 0.6, 4, (2, 1, 3)),
     (64, 2, "potts", TC2, 1, (6,)), (70, 2, "clock", 1.2, 12, (3, 2)), (100, 3, "potts", TC3, 7, (5,)),
     (130, 6, "clock", 0.9, 3, (4, 1)), (127, 2, "potts", 0.5, 13, (4,)), (200, 2, "potts", 5.0, 14, (3,)),
     (192, 32, "potts", 0.4, 15, (3,)), (97, 32, "clock", 0.05, 16, (3,)),
 ])
-@pytest.mark.parametrize("mt", [4, 1])  # merge schedules: blocks of 4 x 4 tiles first; one border kernel
-def test_multi_sweep_calls(swmc, orc, L, q, model, T, seed, calls, mt):
-    _say(f"[fused] L={L} q={q} {model} calls={calls} schedule={mt}")
-    lat = swmc.Lattice(L, q, model, T=T, seed=seed).set_schedule(mt)
+@pytest.mark.parametrize("waves", [4, 8])  # 16 or 8 rows per wave of a tile
+def test_multi_sweep_calls(swmc, orc, L, q, model, T, seed, calls, waves):
+    _say(f"[fused] L={L} q={q} {model} calls={calls} waves={waves}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=seed).set_tile_waves(waves)
     ch = orc.Chain(L, q, model, T=T, seed=seed)
     for n in calls:
         lat.sweep(n, verify=True)
@@ -220,16 +221,16 @@ def test_full_size_L4096(swmc, orc, model, q, T, nsw):
     lat.close()
 
 
-@pytest.mark.parametrize("mt", [1, 4])  # the autotuner picks schedule 1 at this size
+@pytest.mark.parametrize("waves", [4, 8])  # the autotuner picks 4 at this size
 @pytest.mark.parametrize("model,q,T", [("potts", 2, TC2), ("clock", 6, 0.9)])
-def test_full_size_L4096_one_call(swmc, orc, model, q, T, mt):
+def test_full_size_L4096_one_call(swmc, orc, model, q, T, waves):
     # The benchmark's launch configuration: several sweeps in one call, every
     # sweep after the first running the fused flip-and-bond kernel.  Whole
     # states are compared, with the counts of a measured call and the bonds and
     # canonical labels of a verified one.
     L = 4096
-    _say(f"[full, one call] L=4096 {model} q={q} schedule={mt}")
-    lat = swmc.Lattice(L, q, model, T=T, seed=2).set_schedule(mt)
+    _say(f"[full, one call] L=4096 {model} q={q} waves={waves}")
+    lat = swmc.Lattice(L, q, model, T=T, seed=2).set_tile_waves(waves)
     ch = orc.Chain(L, q, model, T=T, seed=2)
     lat.sweep(3, measure=True)
     ch.sweep(3)
@@ -296,9 +297,6 @@ def test_invalid_arguments_raise(swmc):
         lat.labels()  # no SW_VERIFY sweep yet
     with pytest.raises(swmc.SwError):
         lat.sweep(-1)
-    for mt in (0, 3, 8):
-        with pytest.raises(swmc.SwError):
-            lat.set_schedule(mt)
     for w in (0, 2, 5, 16):
         with pytest.raises(swmc.SwError):
             lat.set_tile_waves(w)
