@@ -283,13 +283,16 @@ __device__ __forceinline__ int flipped(uint32_t root_word, int old, int m, int q
 // byte equals the cutoff's high byte (probability 2^-8), so those ties are
 // collected in a tile-wide list and resolved with one draw per tied site.
 // ---------------------------------------------------------------------------
+// kSpinTile (the clock model writing codes): the tile's state and the row
+// below it stay in LDS for the tie resolutions and the codes.
+template <bool kSpinTile>
 struct BondShared {
     uint32_t P[kTileH * kTileW];          // tie list, then the tile forest, then per-root records
     uint64_t raw_r[kTileH];               // right-bond masks of the tile's rows
     uint64_t raw_d[kTileH];               // down-bond masks
     alignas(16) uint8_t halo[kTileH];     // spins of the column right of the tile
-    uint16_t edge[4][kTileW];             // codes: tile-local roots of the perimeter sites
     uint8_t tbl[kSlotsPerTile];           // codes: the previous sweep's draw of each node of the tile
+    uint8_t sp[kSpinTile ? (kTileH + 1) * kTileW : 4];
     uint32_t ntie;
     uint32_t nslots;
 };
@@ -304,34 +307,13 @@ enum BondOutput { kWriteLabels = 0, kWriteCodes = 1, kWriteBonds = 2 };
 // wave's list of roots while they draw.
 constexpr uint32_t kMarkPerimeter = 0x8000u;
 
-// Draw of the root word of node n in a finished node forest.
-__device__ __forceinline__ uint32_t node_root_low(const uint64_t* nodes, uint32_t n, const SweepArgs& a) {
-    uint64_t w = nodes[n];
-    for (uint32_t k = 0; !(static_cast<uint32_t>(w) & kNodeRoot); ++k) {
-        if (k >= a.node_cap) {
-            record_fault(a.ctl, kFaultGlobal);
-            return kNodeRoot;
-        }
-        w = nodes[min(static_cast<uint32_t>(w), a.node_cap - 1u)];  // (clamped: a broken forest stays in bounds)
-    }
-    return static_cast<uint32_t>(w);
-}
-
-// The state after the previous sweep at site j (row y, column xx) from its
-// code and the previous node forest (m: that sweep's mirror).
-template <bool kClock>
-__device__ __forceinline__ int site_from_code(const SweepArgs& a, uint32_t code, int y, int xx, int m) {
-    if (!(code & kCodeNode)) return static_cast<int>(code & 31u);
-    const uint32_t tile = static_cast<uint32_t>((y >> 6) * a.tiles_x + (xx >> 6));
-    const uint32_t v = node_root_low(a.nodes_prev, tile * kSlotsPerTile + (code & 0xFFu), a);
-    return kClock ? flipped<true>(v, static_cast<int>((code >> 8) & 31u), m, a.q) : static_cast<int>(v & 0xFFu);
-}
-
 // kFull: the tile lies inside the lattice (no column or row beyond L), which
 // removes the bounds tests from every row.
 template <int kModel, int kSrc, int kOut, bool kFull, int kW>
-__device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty, BondShared& sh) {
+__device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx, const int ty,
+                                                BondShared<kModel == 1 && kOut == kWriteCodes>& sh) {
     constexpr bool kClock = kModel == 1;
+    constexpr bool kSpinTile = kClock && kOut == kWriteCodes;
     constexpr bool kFused = kSrc == kFromCodes;
     constexpr int RPW = kTileH / kW;  // rows per wave (kW waves per tile)
     static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
@@ -478,14 +460,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
     if (!kFused) __syncthreads();  // halo and cutoffs in LDS (the fused prologue's barrier covers them)
     const bool edge_lane = (lane == nvalid - 1);
-    // clock codes carry each site's value before the flip (five bits, six to
-    // a register)
-    uint32_t old6[(RPW + 5) / 6];
-    if (kClock && kOut == kWriteCodes) {
+    // The clock model's tile state (rows 0 .. nrows, the last one the row
+    // below the tile) for the tie resolutions and the codes, which carry each
+    // site's value before the flip; phase 1's barrier orders the stores.
+    if (kSpinTile) {
 #pragma unroll
-        for (int k = 0; k < (RPW + 5) / 6; ++k) old6[k] = 0u;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) old6[r / 6] |= static_cast<uint32_t>(sreg[r]) << (5 * (r % 6));
+        for (int r = 0; r <= RPW; ++r)
+            if (ly_base + r <= nrows) sh.sp[(ly_base + r) * kTileW + lane] = static_cast<uint8_t>(sreg[r]);
     }
 
     // Phase 1: decisions on the high bytes; ties go to the list.  The right
@@ -554,21 +535,19 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t row = __umul24(y, L);
         const uint32_t i = row + static_cast<uint32_t>(xx);
         const Words4 lo = draw(i, t, kBondLo, k0, k1);
-        // (the fused kernel has no spin array: its spins come from the
-        // previous codes)
-        auto spin_at = [&](int yy, int xc) -> int {
-            const uint32_t j2 = __umul24(yy, L) + static_cast<uint32_t>(xc);
-            if (kFused) return site_from_code<kClock>(a, a.codes_prev[j2], yy, xc, m_prev);
-            return a.spins[j2];
-        };
-        const int s = kClock ? spin_at(y, xx) : 0;  // a Potts tie implies equal spins
+        // (the clock model's codes kernel has the tile's state in LDS; the
+        // other clock kernels read the spin array)
+        auto spin_at = [&](int yy, int xc) -> int { return a.spins[__umul24(yy, L) + static_cast<uint32_t>(xc)]; };
+        const int s = !kClock ? 0 : kSpinTile ? sh.sp[ly * kTileW + lx] : spin_at(y, xx);  // a Potts tie implies equal spins
         if (e & (1u << 12)) {
-            const int sr = kClock ? spin_at(y, (xx + 1 == L) ? 0 : xx + 1) : 0;
+            const int sr = !kClock ? 0
+                           : kSpinTile ? ((lx + 1 < nvalid) ? sh.sp[ly * kTileW + lx + 1] : halo[ly])
+                                       : spin_at(y, (xx + 1 == L) ? 0 : xx + 1);
             const uint32_t c = kClock ? cut[s * q + sr] : c_eq;
             if ((lo.w0 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_r[ly], 1ull << lx);
         }
         if (e & (1u << 13)) {
-            const int sd = kClock ? spin_at((y + 1 == L) ? 0 : y + 1, xx) : 0;
+            const int sd = !kClock ? 0 : kSpinTile ? sh.sp[(ly + 1) * kTileW + lx] : spin_at((y + 1 == L) ? 0 : y + 1, xx);
             const uint32_t c = kClock ? cut[s * q + sd] : c_eq;
             if ((lo.w1 & 0xFFFFFFu) < (c & 0xFFFFFFu)) atomicOr(&raw_d[ly], 1ull << lx);
         }
@@ -766,7 +745,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             if (!(kFull || (col_ok && y < L))) continue;
             const uint32_t rec = P[rootreg[r]] & 0xFFFFu;
             uint32_t code;
-            const int old = kClock ? static_cast<int>((old6[r / 6] >> (5 * (r % 6))) & 31u) : 0;
+            const int old = kClock ? static_cast<int>(sh.sp[(ly_base + r) * kTileW + lane]) : 0;
             if (rec & kMarkPerimeter)
                 code = kCodeNode | (kClock ? static_cast<uint32_t>(old) << 8 : 0u) | (rec & 0xFFu);
             else
@@ -847,7 +826,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
 
 template <int kModel, int kSrc, int kOut, int kW>
 __device__ __forceinline__ void bond_tile(const SweepArgs& a, const int tx, const int ty) {
-    __shared__ BondShared sh;
+    __shared__ BondShared<kModel == 1 && kOut == kWriteCodes> sh;
     if ((tx + 1) * kTileW <= a.L && (ty + 1) * kTileH <= a.L)
         bond_local_tile<kModel, kSrc, kOut, true, kW>(a, tx, ty, sh);
     else
@@ -1558,7 +1537,7 @@ __device__ __forceinline__ void count_q2(const SweepArgs& a, uint32_t block, uin
 // (low half); 8-15: pairs by (s_j - s_i) mod q, right neighbour in the low
 // half, lower neighbour in the high half; 16-23 and 24-31: the correlation
 // pairs at L/4 and L/2, x displacement low, y displacement high.  A lane
-// adds at most 2^13 sites (L <= 46340 with 1024 workgroups of 256 threads),
+// adds at most 2^14 sites (L <= 65535 with 1024 workgroups of 256 threads),
 // so 16-bit halves cannot overflow.  Differences are taken four at a time by
 // byte-wise arithmetic on the packed words (no carries: every byte stays in
 // 0 .. 2q - 1).
@@ -1756,7 +1735,9 @@ __device__ __forceinline__ void hash_sweep(const SweepArgs& a, uint32_t block, u
     const int m = a.model == 1 ? static_cast<int>(a.ctl->mirror) : 0;
     uint64_t hs = 0, hl = 0;
     bool broken = false;
-    for (uint32_t i = block * kHashThreads + threadIdx.x; i < N; i += nblocks * kHashThreads) {
+    // (a 64-bit counter: with N close to 2^32 a 32-bit one would wrap past N)
+    for (uint64_t i64 = block * kHashThreads + threadIdx.x; i64 < N; i64 += nblocks * kHashThreads) {
+        const uint32_t i = static_cast<uint32_t>(i64);
         uint32_t x = i, w = a.labels[i];
         for (uint32_t n = 0; !(w & kRootFlag); ++n) {
             if (n >= kGlobalWalkCap) {
@@ -1818,7 +1799,9 @@ __device__ __forceinline__ void code_hash(const SweepArgs& a, uint32_t block, ui
     const uint32_t N = __umul24(a.L, a.L);
     const int m = a.model == 1 ? static_cast<int>(a.ctl->mirror) : 0;
     uint64_t hs = 0, hl = 0;
-    for (uint32_t i = block * kHashThreads + threadIdx.x; i < N; i += nblocks * kHashThreads) {
+    // (a 64-bit counter: with N close to 2^32 a 32-bit one would wrap past N)
+    for (uint64_t i64 = block * kHashThreads + threadIdx.x; i64 < N; i64 += nblocks * kHashThreads) {
+        const uint32_t i = static_cast<uint32_t>(i64);
         const uint32_t ck = a.codes[i];
         uint32_t v = ck & 31u, lab = a.lroot[i];
         if (ck & kCodeNode) {
@@ -1854,7 +1837,8 @@ __global__ void __launch_bounds__(kHashThreads) k_hash_sum(SweepArgs a, uint32_t
 __global__ void __launch_bounds__(kHashThreads) k_hash_state(const int8_t* spins, const uint32_t* canon, uint32_t n,
                                                              uint64_t* part) {
     uint64_t hs = 0, hl = 0;
-    for (uint32_t i = blockIdx.x * kHashThreads + threadIdx.x; i < n; i += gridDim.x * kHashThreads) {
+    for (uint64_t i64 = blockIdx.x * kHashThreads + threadIdx.x; i64 < n; i64 += gridDim.x * kHashThreads) {
+        const uint32_t i = static_cast<uint32_t>(i64);
         hs += mix64((static_cast<uint64_t>(i) << 8) | static_cast<uint8_t>(spins[i]));
         if (canon) hl += mix64((static_cast<uint64_t>(i) << 32) | canon[i]);
     }
@@ -1897,16 +1881,17 @@ __global__ void __launch_bounds__(kBlock) k_bonds_only(SweepArgs a) {
 
 // Single lattices: the bond kernel with two-level labels, from the spins
 // (a call's first sweep) or from the previous sweep's codes and node forest.
-// Eight waves per SIMD (the scalar registers over the limit spill to vector
-// lanes).
+// Eight waves per SIMD: the register budget of that occupancy caps the
+// scalar registers too, and the ones over the cap spill to vector lanes
+// (leaving the scalar registers uncapped lowers the occupancy and costs more).
 template <int kSrc, int kW>
 __global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) k_code_bond_potts(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     bond_tile<0, kSrc, kWriteCodes, kW>(a, static_cast<int>(t % a.tiles_x), static_cast<int>(t / a.tiles_x));
 }
 
-// The clock model's kernel keeps each site's old value through the labeling
-// and does not fit 64 registers without scratch: seven waves per SIMD.
+// The clock model's kernel keeps its tile's state in LDS, which allows seven
+// workgroups per CU: seven waves per SIMD.
 template <int kSrc, int kW>
 __global__ void __launch_bounds__(kW * 64) __attribute__((amdgpu_waves_per_eu(7, 7))) k_code_bond_clock(SweepArgs a) {
     const uint32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
