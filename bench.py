@@ -167,8 +167,9 @@ def cpu_baseline(cfg, budget_s: float) -> dict:
 
 def bench_batch(args) -> dict:
     """256 q = 3 Potts replicas (L cycling over 64..512, T over [0.9, 1.1] T_c), 500
-    sweeps: batched launches + captured sweep graph, schedule picked by the
-    autotuner, against the same replicas swept one lattice per launch."""
+    sweeps: batched launches, the 500 sweeps captured as one graph launch,
+    merge schedule and waves per tile picked by the autotuner, against the
+    same replicas swept one lattice per launch."""
     import torch
 
     import paper_1202_0635_amd as swmc
@@ -179,8 +180,9 @@ def bench_batch(args) -> dict:
     specs = [(c.L, c.q, c.model, c.T, c.J, c.seed) for c in reps]
     sites = sum(c.L * c.L for c in reps)
     b = swmc.Batch(specs)
-    chosen = b.tune(5)
+    mt, waves = b.tune(5)
     b.sweep(args.warmup)
+    b.sweep(sweeps)  # captures the run of `sweeps` sweeps (one graph), outside the timed region
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.sweep(sweeps)
@@ -203,7 +205,7 @@ def bench_batch(args) -> dict:
             "higher_is_better": True, "n_gpus": 1, "steps": sweeps, "warmup": args.warmup, "dtype": "int8",
             "data": "synthetic",
             "config": {"workload": "potts3_replicas_256_L64-512", "replicas": len(reps), "sites": sites,
-                       "merge_tiles": chosen},
+                       "merge_tiles": mt, "tile_waves": waves, "graph_sweeps": min(sweeps, 512)},
             "batched_spin_updates_per_s": sites * sweeps / t_batch,
             "plain_spin_updates_per_s": sites * sweeps / t_plain,
             "batched_ns_per_update": t_batch * 1e9 / (sites * sweeps), "batched_s": t_batch, "plain_s": t_plain}
@@ -405,7 +407,8 @@ def main() -> int:
                     help="waves per tile of the sweep mode's bond kernel (default: the autotuner's pick)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain replica measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched- and served-vs-plain measurements")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-vs-plain measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -537,6 +540,14 @@ def main() -> int:
         out["batched_vs_plain"] = {k: bb[k] for k in ("value", "config", "batched_spin_updates_per_s",
                                                       "plain_spin_updates_per_s", "batched_s", "plain_s")}
         out["batched_vs_plain"]["sweeps"] = bargs.steps
+        if not args.no_serve:
+            # the first 400 requests of the trace, served against one lattice per launch
+            sargs = argparse.Namespace(requests=400, budget_gib=args.budget_gib, slots=args.slots,
+                                       sweeps_per_step=args.sweeps_per_step)
+            ss = bench_serve(sargs)
+            out["served_vs_plain"] = {"value": ss["value"], "config": ss["config"],
+                                      "results_identical": ss["results_identical"],
+                                      "served": ss["served"], "plain": ss["plain"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)

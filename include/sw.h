@@ -183,7 +183,10 @@ int sw_set_tile_waves(sw_ctx* c, int32_t waves);
 /* Autotuner: times `sweeps` sweeps with 4 and with 8 waves per tile from the
  * current state (three rounds, each choice's fastest counts), restores the
  * state (spins and sweep index) after each, keeps the faster and returns it in
- * *waves.  Allocates a temporary snapshot buffer. */
+ * *waves.  The choice is remembered per (architecture, ceil(log2 L), model, q)
+ * for the process, and across processes in the file named by the environment
+ * variable SWMC_TUNE_CACHE if set; a remembered choice is applied without
+ * timing.  Allocates a temporary snapshot buffer. */
 int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* waves);
 
 /* The cluster labeler (Sec. 3).  SW_LABEL_UNION_FIND (default): tile-local
@@ -242,8 +245,10 @@ int sw_sweep_static(const sw_lattice* p, int8_t* spins, uint64_t t, int32_t nswe
  * Batches: n independent lattices (replicas of any L, q, model, T, seed) swept
  * together.  Every phase of a sweep (Sec. 2 steps (1)-(3)) is one launch over
  * the workgroups of all replicas; one sweep's launches are captured once in a
- * hipGraph and replayed.  Each replica's chain is bit-identical to the same
- * lattice run alone through sw_init/sw_sweep.
+ * hipGraph and replayed: a call of n sweeps is one graph launch for up to 512
+ * sweeps (a run of n sweeps captured once, the last four run lengths kept).
+ * Each replica's chain is bit-identical to the same lattice run alone through
+ * sw_init/sw_sweep.
  * ------------------------------------------------------------------------- */
 typedef struct sw_batch sw_batch;
 
@@ -264,8 +269,22 @@ int sw_batch_read_labels(sw_batch* b, int32_t replica, int32_t* host, size_t n);
 /* As sw_read_hashes, for one replica (the sweeps run with SW_HASH). */
 int sw_batch_read_hashes(sw_batch* b, int32_t replica, uint64_t* out, size_t cap, size_t* n);
 int32_t sw_batch_size(sw_batch* b);
+/* Merge schedule (as sw_set_schedule of the paper's one-level design: 1 = one
+ * device-wide border kernel; 2 or 4 = the inner borders of blocks of that
+ * many tiles per side first joined in LDS) and waves per tile of the batched
+ * bond kernel (4 or 8).  Other values: SW_EINVAL.  Results do not depend on
+ * either; only the time does. */
 int sw_batch_set_schedule(sw_batch* b, int32_t merge_tiles);
-int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles);
+int sw_batch_set_tile_waves(sw_batch* b, int32_t waves);
+/* Autotuner: times a captured run of `sweeps` sweeps for every pair of waves
+ * per tile {4, 8} and merge schedule {1, 2, 4} from the same saved state,
+ * restores the state after each, keeps the fastest pair and returns it in
+ * *merge_tiles and *waves (may be NULL).  Choices are remembered per key
+ * (architecture, total sites bucket, largest L bucket, models present) for the
+ * process, and across processes in the file named by the environment variable
+ * SWMC_TUNE_CACHE if set; a remembered choice is applied without timing.
+ * Allocates a temporary snapshot buffer. */
+int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles, int32_t* waves);
 int sw_batch_profile_read(sw_batch* b, const char** names, int64_t* launches, double* total_ms, int32_t cap,
                           int32_t* nk);
 void sw_batch_free(sw_batch* b);

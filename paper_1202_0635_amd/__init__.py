@@ -305,10 +305,15 @@ class Batch:
         check(_lib.lib().sw_batch_set_schedule(self._b, int(merge_tiles)), "sw_batch_set_schedule")
         return self
 
-    def tune(self, sweeps: int = 5) -> int:
-        out = ctypes.c_int32()
-        check(_lib.lib().sw_batch_tune(self._b, int(sweeps), ctypes.byref(out)), "sw_batch_tune")
-        return int(out.value)
+    def set_tile_waves(self, waves: int):
+        check(_lib.lib().sw_batch_set_tile_waves(self._b, int(waves)), "sw_batch_set_tile_waves")
+        return self
+
+    def tune(self, sweeps: int = 5) -> tuple:
+        """(merge schedule, waves per tile) the autotuner keeps."""
+        mt, w = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.lib().sw_batch_tune(self._b, int(sweeps), ctypes.byref(mt), ctypes.byref(w)), "sw_batch_tune")
+        return int(mt.value), int(w.value)
 
     def profile(self) -> dict:
         names = (ctypes.c_char_p * 8)()

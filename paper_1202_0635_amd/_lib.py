@@ -109,7 +109,9 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_size_t)]),
     "sw_batch_size": (ctypes.c_int32, [ctypes.c_void_p]),
     "sw_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
-    "sw_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "sw_batch_set_tile_waves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sw_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "sw_batch_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_char_p),
                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),

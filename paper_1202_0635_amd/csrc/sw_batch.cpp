@@ -22,6 +22,11 @@ using namespace swmc::host;
 namespace {
 
 constexpr int kSchedules[] = {1, 2, 4};  // first-level merge block sizes the tuner tries
+constexpr int kTileWavesChoices[] = {kWaves, kWavesSmall};
+// A call of n sweeps replays one graph that holds min(n, kMaxGraphSweeps)
+// sweeps (and one for the remainder); the last kGraphCache sizes are kept.
+constexpr int32_t kMaxGraphSweeps = 512;
+constexpr size_t kGraphCache = 4;
 
 constexpr BatchKernel kListKernel[kNumLists] = {kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge,
                                                 kBKFlatten,   kBKFlip,      kBKCounts,     kBKCountSum,
@@ -47,6 +52,8 @@ struct sw_batch {
     bool owns = false;
     bool sticky = false;
     int merge_tiles = kMergeTiles;
+    int tile_waves = kWaves;  // waves per tile of the batched bond kernels
+    std::string arch;         // gcnArchName of the device, for the autotuner cache
     size_t meta_off = 0;
     SweepArgs* d_reps = nullptr;
     uint32_t* d_map[kNumLists] = {};
@@ -54,9 +61,9 @@ struct sw_batch {
     uint32_t blocks[kNumLists] = {};
     std::vector<SweepArgs> h_reps;
     std::vector<uint32_t> h_map[kNumLists], h_begin[kNumLists];
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipStream_t cap_stream = nullptr;  // private stream the sweep is captured on
+    // captured runs of k sweeps (k -> instantiated graph), at most kGraphCache of them
+    std::vector<std::pair<int32_t, hipGraphExec_t>> execs;
+    hipStream_t cap_stream = nullptr;  // private stream the sweeps are captured on
     std::vector<int64_t> ring_host;
     // per-launch timing (SW_PROFILE): event pairs per list
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -122,6 +129,11 @@ size_t arena_bytes(const sw_lattice* ps, int32_t n, size_t* meta_off) {
     return o + meta_bytes(v);
 }
 
+void drop_graphs(sw_batch* b) {
+    for (auto& g : b->execs) (void)hipGraphExecDestroy(g.second);
+    b->execs.clear();
+}
+
 // (Re)build the per-launch maps for the current schedule and upload them.
 int upload_lists(sw_batch* b) {
     const size_t n = b->reps.size();
@@ -166,14 +178,7 @@ int upload_lists(sw_batch* b) {
     }
     SWB_HIP(b, hipMemcpyAsync(b->d_reps, b->h_reps.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, b->stream));
     SWB_HIP(b, hipStreamSynchronize(b->stream));  // host vectors may change after return
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    drop_graphs(b);
     return SW_OK;
 }
 
@@ -192,7 +197,7 @@ int launch_list(sw_batch* b, int l, bool profile, uint32_t row = 0, bool verify 
     if (b->blocks[l] == 0) return SW_OK;
     BatchKernel k = kListKernel[l];
     if (l == kLFlip && verify) k = kBKFlipVerify;
-    const BatchLaunch bl{b->d_reps, b->d_map[l], b->d_begin[l], b->blocks[l]};
+    const BatchLaunch bl{b->d_reps, b->d_map[l], b->d_begin[l], b->blocks[l], b->tile_waves};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
         e0 = take_event(b);
@@ -243,27 +248,40 @@ int flush_hashes(sw_batch* b, int rows) {
     return SW_OK;
 }
 
-// Capture one sweep's launches (on a private stream: the caller's may be the
-// null stream, which cannot be captured) and instantiate the graph; it is
-// replayed on the caller's stream.
-int ensure_graph(sw_batch* b) {
-    if (b->exec) return SW_OK;
+// The instantiated graph of k sweeps' launches, captured on first use (on a
+// private stream: the caller's may be the null stream, which cannot be
+// captured) and replayed on the caller's stream.  The sweep index lives in
+// each replica's control block, so every captured sweep advances the chains.
+int graph_of(sw_batch* b, int32_t k, hipGraphExec_t* out) {
+    for (auto& g : b->execs)
+        if (g.first == k) {
+            *out = g.second;
+            return SW_OK;
+        }
     if (!b->cap_stream) SWB_HIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     hipStream_t user = b->stream;
     b->stream = b->cap_stream;
     hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-    int st = (e == hipSuccess) ? enqueue_sweep(b, false, false) : SW_OK;
+    int st = SW_OK;
+    for (int32_t s = 0; e == hipSuccess && s < k && !st; ++s) st = enqueue_sweep(b, false, false);
     hipGraph_t g = nullptr;
     const hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(b->cap_stream, &g) : hipSuccess;
     b->stream = user;
     if (e != hipSuccess) return bfail(b, e, "hipStreamBeginCapture");
-    if (st) {
+    if (st || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        return st;
+        return st ? st : bfail(b, e2, "hipStreamEndCapture");
     }
-    if (e2 != hipSuccess) return bfail(b, e2, "hipStreamEndCapture");
-    b->graph = g;
-    SWB_HIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return bfail(b, e3, "hipGraphInstantiate");
+    if (b->execs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(b->execs.front().second);
+        b->execs.erase(b->execs.begin());
+    }
+    b->execs.push_back({k, exec});
+    *out = exec;
     return SW_OK;
 }
 
@@ -329,6 +347,7 @@ int sw_batch_init(const sw_lattice* ps, int32_t n, void* dev_mem, size_t bytes, 
 
     sw_batch* b = new sw_batch();
     b->stream = static_cast<hipStream_t>(stream);
+    b->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
     b->meta_off = meta_off;
     if (dev_mem) {
         b->base = static_cast<char*>(dev_mem);
@@ -383,6 +402,16 @@ int sw_batch_set_schedule(sw_batch* b, int32_t merge_tiles) {
     return upload_lists(b);
 }
 
+int sw_batch_set_tile_waves(sw_batch* b, int32_t waves) {
+    const int st = check_batch(b);
+    if (st) return st;
+    if (waves != kWaves && waves != kWavesSmall) return fail(SW_EINVAL, "waves per tile must be 4 or 8");
+    if (waves == b->tile_waves) return SW_OK;
+    b->tile_waves = waves;
+    drop_graphs(b);  // the captured launches name the bond kernel
+    return SW_OK;
+}
+
 int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags) {
     int st = check_batch(b);
     if (st) return st;
@@ -396,10 +425,14 @@ int sw_batch_sweep(sw_batch* b, int32_t nsweeps, uint32_t flags) {
     if (!measure && !profile && !hash && !(flags & SW_NO_GRAPH)) {
         // replay the captured sweep; a verify sweep (the last one) runs uncaptured
         const int32_t plain = verify ? nsweeps - 1 : nsweeps;
-        if (plain > 0) {
-            st = ensure_graph(b);
+        // runs of up to kMaxGraphSweeps sweeps, each one graph launch
+        for (int32_t done = 0; done < plain;) {
+            const int32_t k = (plain - done < kMaxGraphSweeps) ? plain - done : kMaxGraphSweeps;
+            hipGraphExec_t exec = nullptr;
+            st = graph_of(b, k, &exec);
             if (st) return st;
-            for (int32_t s = 0; s < plain; ++s) SWB_HIP(b, hipGraphLaunch(b->exec, b->stream));
+            SWB_HIP(b, hipGraphLaunch(exec, b->stream));
+            done += k;
         }
         if (verify && nsweeps > 0) {
             st = enqueue_sweep(b, false, true);
@@ -505,12 +538,32 @@ int sw_batch_read_labels(sw_batch* b, int32_t replica, int32_t* host, size_t n) 
     return SW_OK;
 }
 
-int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles) {
+int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles, int32_t* waves) {
     int st = check_batch(b);
     if (st) return st;
     if (sweeps <= 0 || !merge_tiles) return fail(SW_EINVAL, "need sweeps > 0 and an output pointer");
-    // Snapshot every replica's spins and control block, time each schedule on
-    // the same states, restore: the chain is left exactly as it was.
+    std::vector<sw_lattice> ps;
+    for (auto& rp : b->reps) ps.push_back(rp.p);
+    const std::string key = tune_key_batch(b->arch, ps.data(), static_cast<int32_t>(ps.size()));
+    int cached = 0;
+    if (tune_cache_get(key, &cached)) {
+        const int mt = cached / 16, w = cached % 16;
+        bool ok = (w == kWaves || w == kWavesSmall);
+        bool mt_ok = false;
+        for (int m : kSchedules) mt_ok = mt_ok || m == mt;
+        if (ok && mt_ok) {
+            st = sw_batch_set_tile_waves(b, w);
+            if (!st) st = sw_batch_set_schedule(b, mt);
+            if (st) return st;
+            *merge_tiles = mt;
+            if (waves) *waves = w;
+            return SW_OK;
+        }
+    }
+    // Snapshot every replica's spins and control block, time each choice of
+    // waves per tile and merge schedule on the same states (one captured run
+    // of `sweeps` sweeps each, after a warm-up sweep), restore: the chain is
+    // left exactly as it was.
     size_t snap = 0;
     for (auto& rp : b->reps) snap += up(static_cast<size_t>(rp.p.L) * rp.p.L) + up(sizeof(Control));
     void* tmp = nullptr;
@@ -532,31 +585,34 @@ int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles) {
         }
         return hipSuccess;
     };
-    const int original = b->merge_tiles;
-    int best = original;
+    int best_mt = b->merge_tiles, best_w = b->tile_waves;
     float best_ms = 0.0f;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = save_restore(true);
-    for (int mt : kSchedules) {
-        if (e != hipSuccess) break;
-        st = sw_batch_set_schedule(b, mt);
-        if (st) break;
-        st = sw_batch_sweep(b, 1, 0);  // warm the graph
-        if (st) break;
-        e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess) st = sw_batch_sweep(b, sweeps, 0);
-        if (e == hipSuccess && !st) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess && !st) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess && !st) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && !st && (best_ms == 0.0f || ms < best_ms)) {
-            best_ms = ms;
-            best = mt;
+    for (int w : kTileWavesChoices) {
+        for (int mt : kSchedules) {
+            if (e != hipSuccess || st) break;
+            st = sw_batch_set_tile_waves(b, w);
+            if (!st) st = sw_batch_set_schedule(b, mt);
+            if (!st) st = sw_batch_sweep(b, 1, 0);  // capture and warm
+            if (!st) st = sw_batch_sweep(b, sweeps, 0);  // capture the timed run
+            if (!st) e = save_restore(false);
+            if (st || e != hipSuccess) break;
+            e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) st = sw_batch_sweep(b, sweeps, 0);
+            if (e == hipSuccess && !st) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess && !st) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess && !st) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && !st && (best_ms == 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best_mt = mt;
+                best_w = w;
+            }
+            if (e == hipSuccess && !st) e = save_restore(false);
         }
-        if (e == hipSuccess && !st) e = save_restore(false);
-        if (st) break;
     }
     if (e == hipSuccess && !st) e = hipStreamSynchronize(b->stream);
     if (e0) (void)hipEventDestroy(e0);
@@ -565,9 +621,12 @@ int sw_batch_tune(sw_batch* b, int32_t sweeps, int32_t* merge_tiles) {
     if (st) return st;
     if (e != hipSuccess) return bfail(b, e, "sw_batch_tune");
     for (auto& rp : b->reps) rp.have_canon = false;
-    st = sw_batch_set_schedule(b, best);
+    st = sw_batch_set_tile_waves(b, best_w);
+    if (!st) st = sw_batch_set_schedule(b, best_mt);
     if (st) return st;
-    *merge_tiles = best;
+    tune_cache_put(key, best_mt * 16 + best_w);
+    *merge_tiles = best_mt;
+    if (waves) *waves = best_w;
     return SW_OK;
 }
 
@@ -605,8 +664,7 @@ int32_t sw_batch_size(sw_batch* b) { return b ? static_cast<int32_t>(b->reps.siz
 void sw_batch_free(sw_batch* b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    drop_graphs(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (auto& pe : b->pending) {
         (void)hipEventDestroy(pe.second.first);

@@ -6,7 +6,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "sw.h"
@@ -235,6 +239,79 @@ SweepArgs make_args(const sw_lattice& p, char* base, const Layout& lay) {
     a.key0 = static_cast<uint32_t>(p.seed);
     a.key1 = static_cast<uint32_t>(p.seed >> 32);
     return a;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner cache.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mutex;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+const char* tune_file() {
+    const char* f = std::getenv("SWMC_TUNE_CACHE");
+    return (f && *f) ? f : nullptr;
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* f = tune_file();
+    if (!f) return;
+    std::ifstream in(f);
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t sp = line.rfind(' ');
+        if (sp == std::string::npos || sp == 0) continue;
+        char* end = nullptr;
+        const long v = std::strtol(line.c_str() + sp + 1, &end, 10);
+        if (end == line.c_str() + sp + 1) continue;
+        g_tune[line.substr(0, sp)] = static_cast<int>(v);
+    }
+}
+
+int ceil_log2(uint64_t v) {
+    int k = 0;
+    while ((1ull << k) < v) ++k;
+    return k;
+}
+}  // namespace
+
+bool tune_cache_get(const std::string& key, int* choice) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    tune_load_locked();
+    const auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *choice = it->second;
+    return true;
+}
+
+void tune_cache_put(const std::string& key, int choice) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    tune_load_locked();
+    g_tune[key] = choice;
+    if (const char* f = tune_file()) {
+        std::ofstream out(f, std::ios::app);
+        out << key << ' ' << choice << '\n';
+    }
+}
+
+std::string tune_key_lattice(const std::string& arch, const sw_lattice& p) {
+    return "lattice " + arch + " L2^" + std::to_string(ceil_log2(static_cast<uint64_t>(p.L))) + " model" +
+           std::to_string(p.model) + " q" + std::to_string(p.q);
+}
+
+std::string tune_key_batch(const std::string& arch, const sw_lattice* ps, int32_t n) {
+    uint64_t sites = 0;
+    int lmax = 0, models = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        sites += static_cast<uint64_t>(ps[r].L) * static_cast<uint64_t>(ps[r].L);
+        lmax = ps[r].L > lmax ? ps[r].L : lmax;
+        models |= 1 << ps[r].model;
+    }
+    return "batch " + arch + " sites2^" + std::to_string(ceil_log2(sites)) + " Lmax2^" +
+           std::to_string(ceil_log2(static_cast<uint64_t>(lmax))) + " models" + std::to_string(models);
 }
 
 void fill_obs(const sw_lattice& p, const int64_t* row, uint64_t t, const Sums& sums, sw_obs* out) {

@@ -65,6 +65,16 @@ extern const Control kFreshControl;
 const char* fault_text(uint32_t bits);
 int fault_status(uint32_t bits);
 
+// Autotuner choices, remembered per key for the life of the process and, when
+// the environment variable SWMC_TUNE_CACHE names a file, across processes
+// (one "key choice" line per entry; later lines win).  Keys name what the
+// choice depends on: the GPU architecture, the lattice size bucket
+// (ceil(log2 L), or of the total sites of a batch), the model and q.
+bool tune_cache_get(const std::string& key, int* choice);
+void tune_cache_put(const std::string& key, int choice);
+std::string tune_key_lattice(const std::string& arch, const sw_lattice& p);
+std::string tune_key_batch(const std::string& arch, const sw_lattice* ps, int32_t n);
+
 // One record of a per-sweep hash stream: the sweep index of the state after
 // the sweep, H_s of that state and H_l of its canonical labels.
 struct HashRecord {

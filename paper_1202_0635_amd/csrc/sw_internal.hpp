@@ -196,6 +196,7 @@ struct BatchLaunch {
     const uint32_t* map;    // device: workgroup -> replica
     const uint32_t* begin;  // device: replica -> first workgroup of this launch
     uint32_t blocks;        // workgroups of the launch
+    int waves;              // bond kernels: waves per tile (kWaves or kWavesSmall)
 };
 hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint32_t row);
 

@@ -2070,11 +2070,11 @@ __device__ __forceinline__ uint32_t batch_replica(const BatchMap& m, uint32_t* l
     return r;
 }
 
-template <int kModel>
-__global__ void __launch_bounds__(kBlock) kb_bond_local(BatchMap m) {
+template <int kModel, int kW>
+__global__ void __launch_bounds__(kW * 64) kb_bond_local(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    bond_tile<kModel, kFromSpins, kWriteLabels, kWaves>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
+    bond_tile<kModel, kFromSpins, kWriteLabels, kW>(a, static_cast<int>(local % a.tiles_x), static_cast<int>(local / a.tiles_x));
 }
 
 __global__ void __launch_bounds__(kMergeThreads) kb_block_merge(BatchMap m) {
@@ -2296,8 +2296,18 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
     const BatchMap m{l.reps, l.map, l.begin};
     const dim3 grid(l.blocks);
     switch (k) {
-        case kBKBondPotts: hipLaunchKernelGGL(kb_bond_local<0>, grid, dim3(kBlock), 0, s, m); break;
-        case kBKBondClock: hipLaunchKernelGGL(kb_bond_local<1>, grid, dim3(kBlock), cut_bytes(32), s, m); break;
+        case kBKBondPotts:
+            if (l.waves == kWavesSmall)
+                hipLaunchKernelGGL((kb_bond_local<0, kWavesSmall>), grid, dim3(kWavesSmall * 64), 0, s, m);
+            else
+                hipLaunchKernelGGL((kb_bond_local<0, kWaves>), grid, dim3(kWaves * 64), 0, s, m);
+            break;
+        case kBKBondClock:
+            if (l.waves == kWavesSmall)
+                hipLaunchKernelGGL((kb_bond_local<1, kWavesSmall>), grid, dim3(kWavesSmall * 64), cut_bytes(32), s, m);
+            else
+                hipLaunchKernelGGL((kb_bond_local<1, kWaves>), grid, dim3(kWaves * 64), cut_bytes(32), s, m);
+            break;
         case kBKBlockMerge: hipLaunchKernelGGL(kb_block_merge, grid, dim3(kMergeThreads), 0, s, m); break;
         case kBKBorderMerge: hipLaunchKernelGGL(kb_border_merge, grid, dim3(256), 0, s, m); break;
         case kBKFlatten: hipLaunchKernelGGL(kb_flatten, grid, dim3(256), 0, s, m); break;

@@ -34,6 +34,7 @@ struct sw_ctx {
     std::vector<hipEvent_t> free_events;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     int labeler = kUnionFind;
+    std::string arch;  // gcnArchName of the device, for the autotuner cache
     // counts of measured sweeps run on a second stream (made on first use,
     // default priority), ordered against the sweep by events
     hipStream_t side = nullptr;
@@ -162,6 +163,7 @@ int sw_init(const sw_lattice* p, void* dev_mem, size_t bytes, void* stream, sw_c
 
     sw_ctx* c = new sw_ctx();
     c->p = *p;
+    c->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
     c->stream = static_cast<hipStream_t>(stream);
     c->lay = lay;
     if (dev_mem) {
@@ -591,6 +593,13 @@ int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* waves) {
     int st = check_ctx(c);
     if (st) return st;
     if (sweeps <= 0 || !waves) return fail(SW_EINVAL, "need sweeps > 0 and an output pointer");
+    const std::string key = tune_key_lattice(c->arch, c->p);
+    int cached = 0;
+    if (tune_cache_get(key, &cached) && (cached == kWaves || cached == kWavesSmall)) {
+        c->args.tile_waves = cached;
+        *waves = cached;
+        return SW_OK;
+    }
     const size_t N = static_cast<size_t>(c->p.L) * c->p.L;
     void* tmp = nullptr;
     SW_HIP(c, hipMalloc(&tmp, up(N) + up(sizeof(Control))));
@@ -638,6 +647,7 @@ int sw_tune(sw_ctx* c, int32_t sweeps, int32_t* waves) {
     if (e != hipSuccess) return device_fail(c, e, "sw_tune");
     c->args.tile_waves = best;
     c->have_canon = false;
+    tune_cache_put(key, best);
     *waves = best;
     return SW_OK;
 }

@@ -182,7 +182,7 @@ struct HipExec {
         for (int sweep = 0; sweep < sweeps; ++sweep)
             for (int l : kSweepLists) {
                 if (blocks[l] == 0) continue;
-                const BatchLaunch bl{d_reps, d_map[l], d_begin[l], blocks[l]};
+                const BatchLaunch bl{d_reps, d_map[l], d_begin[l], blocks[l], kWaves};
                 SWS_HIP(s, launch_batch(kKernelOf[l], bl, s->stream, 0));
             }
         return SW_OK;

@@ -114,15 +114,18 @@ def test_batch_schedules_and_tune(swmc, orc):
     ref.sweep(6)
     with pytest.raises(swmc.SwError):
         swmc.Batch(specs[:1]).set_schedule(8)
-    for mt in (1, 2):
-        b = swmc.Batch(specs).set_schedule(mt)
+    with pytest.raises(swmc.SwError):
+        swmc.Batch(specs[:1]).set_tile_waves(6)
+    for mt, w in ((1, 4), (2, 4), (4, 8), (1, 8)):
+        b = swmc.Batch(specs).set_schedule(mt).set_tile_waves(w)
         b.sweep(6)
         for r in range(len(specs)):
-            assert np.array_equal(b.spins(r), ref.spins(r)), (mt, r)
+            assert np.array_equal(b.spins(r), ref.spins(r)), (mt, w, r)
         b.close()
     b = swmc.Batch(specs)
     b.sweep(3)
-    assert b.tune(2) in (1, 2, 4)
+    mt, w = b.tune(2)
+    assert mt in (1, 2, 4) and w in (4, 8)
     b.sweep(3)
     for r in range(len(specs)):
         assert np.array_equal(b.spins(r), ref.spins(r))
@@ -150,3 +153,24 @@ def test_profiles_name_every_launch(swmc):
     for name, n in expect.items():
         assert prof[name][0] == n, (name, prof)
     lat.close()
+
+
+def test_batch_graph_runs_of_many_sweeps(swmc):
+    # one call of n sweeps replays one captured run of n sweeps (up to 512, then
+    # the remainder): the same states as sweeps taken one call at a time, with
+    # and without the graph
+    specs = [(L, q, m, T, 1.0, 300 + i) for i, (L, q, m, T) in
+             enumerate([(64, 2, "potts", TC2), (130, 3, "potts", TC3), (70, 6, "clock", 0.9), (256, 2, "potts", 1.5)])]
+    _say("[batch] graph runs")
+    a = swmc.Batch(specs)
+    a.sweep(700)  # a run of 512 and one of 188
+    a.sweep(37)
+    b = swmc.Batch(specs)
+    for n in (1, 2, 5, 100, 3):
+        b.sweep(n, graph=False)
+    b.sweep(737 - 111)
+    for r in range(len(specs)):
+        assert np.array_equal(a.spins(r), b.spins(r)), r
+        assert a.measure(r)["t"] == b.measure(r)["t"] == 737
+    a.close()
+    b.close()

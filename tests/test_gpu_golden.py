@@ -122,8 +122,9 @@ def replica_golden():
 
 
 # The 256 q = 3 replicas (L over 64 ... 512, T over [0.9, 1.1] T_c) at sweeps
-# 1, 10, 100 and 500: uncaptured sweeps with hashes, and the captured-graph
-# path after the autotuner's choice, compared at the end by the state hash.
+# 1, 10, 100 and 500: uncaptured sweeps with hashes, and the 500 sweeps as one
+# captured graph after the autotuner's choice, compared at the end by the state
+# hash.
 def test_replica_mix_256(swmc):
     from paper_1202_0635_amd.workloads import replica_mix_q3
 
@@ -139,7 +140,7 @@ def test_replica_mix_256(swmc):
         sub = {t: v for t, v in gold[r].items()}
         _check_stream(got[np.isin(got[:, 0], list(sub))], sub, f"replica {r}")
     b.close()
-    _say("[golden C4] 256 replicas, tuned schedule, 500 graph replays")
+    _say("[golden C4] 256 replicas, tuned schedule, one graph of 500 sweeps")
     b = swmc.Batch(specs)
     b.tune(3)
     b.sweep(500)
