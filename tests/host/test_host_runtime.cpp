@@ -1,7 +1,8 @@
 // Host-only tests of libswmc's runtime pieces, built with g++ under
 // AddressSanitizer and UndefinedBehaviorSanitizer (tests/test_host_sanitized.py):
 //   * parameter checks, the cutoff table, the arena layout, observables from
-//     counts and the decoding of device fault bits (sw_host.cpp);
+//     counts, the decoding of device fault bits and the autotuner cache
+//     (sw_host.cpp);
 //   * the request server's policy (sw_sched.hpp) driven by a recording fake
 //     executor: arrival-order admission with head-of-line waiting, the memory
 //     budget, slot reuse, retirement after exactly the requested sweeps,
@@ -11,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <random>
 #include <set>
@@ -349,6 +351,45 @@ static void test_head_of_line() {
     CHECK(ex.admitted.size() == 3 && ex.admitted[1] == 1 && ex.admitted[2] == 2);
 }
 
+// The autotuner cache: keys bucket lattices by ceil(log2 L) (batches by total
+// sites and largest L) and separate models, q and architectures; the file
+// named by SWMC_TUNE_CACHE (the test driver seeds it with one good line and
+// malformed ones) is read once, and every new choice is appended to it.
+static void test_tune_cache() {
+    const std::string f = std::getenv("SWMC_TUNE_CACHE") ? std::getenv("SWMC_TUNE_CACHE") : "";
+    CHECK(!f.empty());
+    CHECK(tune_key_lattice("gfx950", lat(33, 2, SW_POTTS, 1.0)) == tune_key_lattice("gfx950", lat(64, 2, SW_POTTS, 1.0)));
+    CHECK(tune_key_lattice("gfx950", lat(64, 2, SW_POTTS, 1.0)) != tune_key_lattice("gfx950", lat(65, 2, SW_POTTS, 1.0)));
+    CHECK(tune_key_lattice("gfx950", lat(64, 2, SW_POTTS, 1.0)) != tune_key_lattice("gfx950", lat(64, 3, SW_POTTS, 1.0)));
+    CHECK(tune_key_lattice("gfx950", lat(64, 6, SW_POTTS, 1.0)) != tune_key_lattice("gfx950", lat(64, 6, SW_CLOCK, 1.0)));
+    CHECK(tune_key_lattice("gfx950", lat(64, 2, SW_POTTS, 1.0)) != tune_key_lattice("gfx942", lat(64, 2, SW_POTTS, 1.0)));
+    // temperature, coupling and seed do not enter the key
+    CHECK(tune_key_lattice("gfx950", lat(64, 2, SW_POTTS, 1.0, 1)) == tune_key_lattice("gfx950", lat(64, 2, SW_POTTS, 2.0, 9)));
+    const sw_lattice one[1] = {lat(32, 2, SW_POTTS, 1.0)};
+    const sw_lattice mix[2] = {lat(32, 2, SW_POTTS, 1.0), lat(20, 6, SW_CLOCK, 1.0)};
+    CHECK(tune_key_batch("gfx950", one, 1) == "batch gfx950 sites2^10 Lmax2^5 models1");
+    CHECK(tune_key_batch("gfx950", mix, 2) != tune_key_batch("gfx950", one, 1));
+    int v = -1;
+    CHECK(tune_cache_get("batch gfx950 sites2^10 Lmax2^5 models1", &v) && v == 33);  // seeded in the file
+    CHECK(!tune_cache_get(tune_key_batch("gfx950", mix, 2), &v));
+    CHECK(!tune_cache_get("junk", &v));
+    const std::string k = tune_key_lattice("gfx950", lat(4096, 2, SW_POTTS, 1.0));
+    CHECK(!tune_cache_get(k, &v));
+    tune_cache_put(k, 4);
+    CHECK(tune_cache_get(k, &v) && v == 4);
+    tune_cache_put(k, 8);  // a later choice wins, here and when the file is read again
+    CHECK(tune_cache_get(k, &v) && v == 8);
+    std::ifstream in(f);
+    std::string line, last;
+    int lines = 0;
+    while (std::getline(in, line)) {
+        ++lines;
+        last = line;
+    }
+    CHECK(last == k + " 8");
+    CHECK(lines >= 3);
+}
+
 int main() {
     test_params();
     test_tables();
@@ -358,6 +399,7 @@ int main() {
     test_pool();
     test_server_policy();
     test_head_of_line();
+    test_tune_cache();
     if (g_failures) {
         std::fprintf(stderr, "%d check(s) failed\n", g_failures);
         return 1;
