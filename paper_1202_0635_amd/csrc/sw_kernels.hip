@@ -650,53 +650,49 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     }
     __syncthreads();
 
-    // Phase 3: tile-local roots.  Run starts are pointed straight at their
-    // root, after which any site reaches its root in two loads.  The walks
-    // only read: a wave stores only into its own run starts, so no store can
-    // replace a root another wave has just placed (a halving store could).
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        if (__builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1))) {
-            // usually the run's label is itself a root: two loads, no store
-            const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
-            const uint32_t p = lds_load(&P[self]);
-            if (p != self) {
-                uint32_t x = p, gp = lds_load(&P[p]);
-                if (gp != p) {
-                    for (uint32_t n = 0; gp != x; ++n) {
-                        if (n >= kLdsWalkCap) {
-                            record_fault(a.ctl, kFaultLds);
-                            break;
-                        }
-                        x = gp;
-                        gp = lds_load(&P[x]);
-                    }
-                    lds_store(&P[self], x & (kLdsWalkCap - 1u));
-                }
-            }
-        }
+    // Roots.  After phase 2b the forest is final and is only read: a site
+    // follows its parents (its run's first site, the run's label, ...) to the
+    // root.  The walks of all rows of a wave advance together, one level per
+    // step, with every level's loads issued at once; a root is its own parent,
+    // so a walk that has arrived stays put, and the steps end when no site of
+    // the wave moved.  The code output also walks from the perimeter sites
+    // (edges as in the border record: right column, bottom row, left column,
+    // top row), one edge per wave.
+    constexpr uint32_t kM = kLdsWalkCap - 1u;
+    constexpr bool kCodes = kOut == kWriteCodes;
+    const uint32_t e = threadIdx.x >> 6, pos = ulane;
+    const bool perim = kCodes && threadIdx.x < 4 * kTileW && static_cast<int>(pos) < ((e & 1u) ? nvalid : nrows);
+    uint32_t proot = 0;
+    if (perim) {
+        const uint32_t col = (e == 0) ? static_cast<uint32_t>(nvalid - 1) : (e == 2) ? 0u : pos;
+        const uint32_t row = (e == 1) ? static_cast<uint32_t>(nrows - 1) : (e == 3) ? 0u : pos;
+        proot = row * kTileW + col;
     }
-    __syncthreads();  // every run's first site holds its root
     uint32_t rootreg[RPW];
-    if (kOut == kWriteCodes) {
-        // A run's first site holds its root and a root holds itself, so any
-        // site's root is two loads away.
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) rootreg[r] = P[(ly_base + r) * kTileW + lane] & kM;
+    if (kCodes) proot = P[proot] & kM;
+    for (uint32_t n = 0;; ++n) {
+        bool moved = false;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
-            rootreg[r] = P[P[self] & (kLdsWalkCap - 1u)] & (kLdsWalkCap - 1u);
+            const uint32_t up = P[rootreg[r]] & kM;
+            moved = moved || up != rootreg[r];
+            rootreg[r] = up;
         }
-        // Roots of the perimeter sites (edges as in the border record: right
-        // column, bottom row, left column, top row), one edge per wave.
-        const uint32_t e = threadIdx.x >> 6, pos = ulane;
-        const bool perim = threadIdx.x < 4 * kTileW && static_cast<int>(pos) < ((e & 1u) ? nvalid : nrows);
-        uint32_t proot = 0;
-        if (perim) {
-            const uint32_t col = (e == 0) ? static_cast<uint32_t>(nvalid - 1) : (e == 2) ? 0u : pos;
-            const uint32_t row = (e == 1) ? static_cast<uint32_t>(nrows - 1) : (e == 3) ? 0u : pos;
-            proot = P[P[row * kTileW + col] & (kLdsWalkCap - 1u)] & (kLdsWalkCap - 1u);
+        if (kCodes) {
+            const uint32_t up = P[proot] & kM;
+            moved = moved || up != proot;
+            proot = up;
         }
-        __syncthreads();  // every root is read: P now holds per-root records
+        if (__ballot(moved) == 0ull) break;
+        if (n >= kLdsWalkCap) {
+            record_fault(a.ctl, kFaultLds);
+            break;
+        }
+    }
+    __syncthreads();  // every root is read: P may now be rewritten
+    if (kCodes) {
         // Every component that reaches the perimeter becomes a node: the
         // first perimeter site to mark its root takes the next slot.
         if (perim) {
@@ -755,16 +751,6 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
             if (a.lroot) (a.lroot + rb)[ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
         }
         return;
-    }
-    // One-level labels: every wave reads only its own rows of P (a run's
-    // first site holds its root, any other site points at its run's first
-    // site), since a wave's rows of P hold its root list afterwards.
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        const uint32_t self = static_cast<uint32_t>((ly_base + r) * kTileW + lane);
-        const uint32_t p = P[self];
-        rootreg[r] = (__builtin_amdgcn_inverse_ballot_w64(~((uniform64(raw_r[ly_base + r]) & in_tile_r) << 1)) ? p : P[p]) &
-                     (kLdsWalkCap - 1u);
     }
     // Border record, edge roots (global site indices), from the registers of
     // the waves that own the rows: right column (edge 0) by the lane of the
