@@ -385,6 +385,18 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     };
     auto row_ok = [&](int r) -> bool { return kFull || (col_ok && y_base + r <= L); };
     uint32_t cw[RPW + 1];  // fused: the previous codes of this lane's sites
+    // Phase 1's bond draws depend only on the site and the sweep: one draw per
+    // 8-row group of the lane's column, taken while the state loads are in
+    // flight.
+    Words4 hiw[RPW / 8];
+    auto bond_draws = [&]() {
+#pragma unroll
+        for (int g = 0; g < RPW / 8; ++g) {
+            const int yb = y0 + ly_base + g * 8;  // multiple of 8
+            hiw[g] = {0, 0, 0, 0};
+            if (kFull || (col_ok && yb < L)) hiw[g] = draw(__umul24(yb >> 3, L) + static_cast<uint32_t>(x), t, kBondHi, k0, k1);
+        }
+    };
     if (kFused) {
         // The loads that depend on nothing are issued first: this lane's
         // previous codes, the halo site's, and for thread k below the tile's
@@ -403,6 +415,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t hc = halo_lane ? static_cast<uint32_t>(a.codes_prev[ih]) : 0u;
         const bool t_walk = threadIdx.x < ns;
         uint64_t tw = t_walk ? a.nodes_prev[static_cast<uint32_t>(tile) * kSlotsPerTile + threadIdx.x] : kNodeRoot;
+        bond_draws();
         int rf = -1;  // uniform
 #pragma unroll
         for (int r = 0; r <= RPW; ++r)
@@ -457,6 +470,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         for (int r = 0; r <= RPW; ++r) {
             sreg[r] = row_ok(r) ? (a.spins + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0)))[ulane] : 0;
         }
+        bond_draws();
     }
     if (!kFused) __syncthreads();  // halo and cutoffs in LDS (the fused prologue's barrier covers them)
     const bool edge_lane = (lane == nvalid - 1);
@@ -481,8 +495,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     for (int g = 0; g < RPW / 8; ++g) {
         const int ly0 = ly_base + g * 8;
         const int yb = y0 + ly0;  // multiple of 8
-        Words4 hi = {0, 0, 0, 0};
-        if (kFull || (col_ok && yb < L)) hi = draw(__umul24(yb >> 3, L) + static_cast<uint32_t>(x), t, kBondHi, k0, k1);
+        const Words4 hi = hiw[g];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int r = g * 8 + k;
