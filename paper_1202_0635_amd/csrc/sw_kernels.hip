@@ -597,53 +597,66 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         if (lane < kBorderMasks) a.border_bonds[tile * kBorderMasks + lane] = v;
     }
     // Phase 2: each wave labels its strip of rows in raster order, as the
-    // Hoshen-Kopelman scan does (Sec. 2): a run of the current row takes the
-    // smallest root among the sites above it that it is bonded to (or becomes
-    // a new root at its first site), and the other roots it touches are
-    // joined to that one.  P holds, for each site, its run's first site, and
-    // for a run's first site, the run's label.
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
-    // A bond mask read from LDS is uniform: two lane reads put it in scalar
-    // registers, where the test of a lane's bit costs no vector instruction.
-    auto uniform64 = [](uint64_t v) -> uint64_t {
-        const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-        const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-        return (static_cast<uint64_t>(hi) << 32) | lo;
-    };
+    // Hoshen-Kopelman scan does (Sec. 2).  P holds, for each site, its run's
+    // first site, and for a run's first site, the run's label (a link to a
+    // smaller index, or itself).  A bond mask held in scalar registers tests
+    // a lane's bit with no vector instruction.
     const uint64_t le_lane = ~0ull >> (63 - lane);  // this lane and the lanes below it
     {
-        uint32_t lab_prev = kNone;
-        uint64_t d_above = 0;  // down bonds of the row above (within the strip)
+        // The wave's row masks are read once, one row per lane, and taken row
+        // by row into scalar registers with lane reads.
+        const uint64_t rr_lane = (lane < RPW) ? raw_r[ly_base + lane] : 0ull;
+        const uint64_t dd_lane = (lane < RPW) ? raw_d[ly_base + lane] : 0ull;
+        auto lane64 = [](uint64_t v, int k) -> uint64_t {
+            const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), k);
+            const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), k);
+            return (static_cast<uint64_t>(hi) << 32) | lo;
+        };
+        // Every site points at its run's first site, which starts as the
+        // run's own label.
+        uint32_t node[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int ly = ly_base + r;
-            const uint64_t starts = ~((uniform64(raw_r[ly]) & in_tile_r) << 1);  // first sites of the runs
-            const int start = 63 - __clzll(starts & le_lane);
-            const uint32_t node = static_cast<uint32_t>(ly * kTileW + start);
-            // the label above is usually still a root: one load, and the
-            // find loop runs only where it is not
-            uint32_t cand = kNone;
-            if (r > 0 && (kFull || y0 + ly < L) && __builtin_amdgcn_inverse_ballot_w64(d_above)) {
-                const uint32_t p = lds_load(&P[lab_prev]);
-                cand = (p == lab_prev) ? p : lds_find_from(P, lab_prev, p, a.ctl);
-            }
-            // every site points at its run's first site; the first site's
-            // entry then takes the smallest root above the run (roots of
-            // earlier rows have smaller indices), which is the run's label
-            P[ly * kTileW + lane] = node;
-            __builtin_amdgcn_wave_barrier();
-            if (cand != kNone) atomicMin(&P[node], cand);
-            __builtin_amdgcn_wave_barrier();
-            const uint32_t lab = lds_load(&P[node]);
-            // cand and lab were roots when found (lab < cand); link cand under
-            // lab at once, and join its new parent too if it was linked meanwhile
-            if (cand != kNone && cand != lab) {
-                const uint32_t old = __hip_atomic_fetch_min(&P[cand], lab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (old != cand) lds_union(P, old, lab, a.ctl);
-            }
-            lab_prev = lab;
-            d_above = uniform64(raw_d[ly]);
+            const uint64_t starts = ~((lane64(rr_lane, r) & in_tile_r) << 1);  // first sites of the runs
+            node[r] = static_cast<uint32_t>(ly * kTileW + 63 - __clzll(starts & le_lane));
+            P[ly * kTileW + lane] = node[r];
         }
+        // Rows in raster order: a run takes the smallest label among the runs
+        // above it that it is bonded to (labels of earlier rows are smaller),
+        // and each other label it touches is lowered to that one.  A label
+        // that has been lowered before is no longer a root: lowering it again
+        // returns its parent, which must then be joined as well.  That check
+        // of a row waits until the next row's loads are issued.
+        uint32_t lab_prev = node[0];
+        uint32_t old_p = 0, tgt_p = 0, lab_p = 0;
+        bool need_p = false;
+        auto join_parent = [&](bool need, uint32_t old, uint32_t tgt, uint32_t lab) {
+            const bool bad = need && old != tgt && old != lab;
+            if (__ballot(bad)) {
+                if (bad) lds_union(P, old, lab, a.ctl);
+            }
+        };
+#pragma unroll
+        for (int r = 1; r < RPW; ++r) {
+            const int ly = ly_base + r;
+            const uint64_t d_above = (kFull || y0 + ly < L) ? lane64(dd_lane, r - 1) : 0ull;
+            const bool up = __builtin_amdgcn_inverse_ballot_w64(d_above);
+            __builtin_amdgcn_wave_barrier();
+            if (up) atomicMin(&P[node[r]], lab_prev);
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t lab = lds_load(&P[node[r]]);
+            if (r > 1) join_parent(need_p, old_p, tgt_p, lab_p);
+            const bool need = up && lab_prev != lab;
+            uint32_t old = lab_prev;
+            if (need) old = __hip_atomic_fetch_min(&P[lab_prev], lab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            need_p = need;
+            old_p = old;
+            tgt_p = lab_prev;
+            lab_p = lab;
+            lab_prev = lab;
+        }
+        join_parent(need_p, old_p, tgt_p, lab_p);
     }
     __syncthreads();
 
