@@ -451,10 +451,13 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const int sf = value_of(fc, fw);
         if (wave == 0) halo[lane] = halo_lane ? static_cast<uint8_t>(value_of(hc, hw)) : 0;
         __syncthreads();  // the node draws, the halo and the cutoffs in LDS
+        // (Potts: an inner site's code is its value; the table is read for
+        // every site and used for a node's.)
         auto own = [&](uint32_t c) -> int {
-            if (!(c & kCodeNode)) return static_cast<int>(c & 31u);
             const uint32_t v = sh.tbl[c & 0xFFu];
-            return kClock ? flipped<true>(v, static_cast<int>((c >> 8) & 31u), m_prev, q) : static_cast<int>(v);
+            if (!kClock) return static_cast<int>((c & kCodeNode) ? v : c);
+            if (!(c & kCodeNode)) return static_cast<int>(c & 31u);
+            return flipped<true>(v, static_cast<int>((c >> 8) & 31u), m_prev, q);
         };
 #pragma unroll
         for (int r = 0; r <= RPW; ++r) sreg[r] = !row_ok(r) ? 0 : (r == rf) ? sf : own(cw[r]);
@@ -684,7 +687,6 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     // the wave moved.  The code output also walks from the perimeter sites
     // (edges as in the border record: right column, bottom row, left column,
     // top row), one edge per wave.
-    constexpr uint32_t kM = kLdsWalkCap - 1u;
     constexpr bool kCodes = kOut == kWriteCodes;
     const uint32_t e = threadIdx.x >> 6, pos = ulane;
     const bool perim = kCodes && threadIdx.x < 4 * kTileW && static_cast<int>(pos) < ((e & 1u) ? nvalid : nrows);
@@ -694,24 +696,38 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const uint32_t row = (e == 1) ? static_cast<uint32_t>(nrows - 1) : (e == 3) ? 0u : pos;
         proot = row * kTileW + col;
     }
-    uint32_t rootreg[RPW];
+    // The walks step two levels per round, between two register sets, so
+    // that no copies are needed; a set that did not move holds the roots.
+    // (Entries are tile indices; LDS reads out of range return zero, and the
+    // round count is bounded, so a broken forest cannot fault or hang here.)
+    uint32_t rootreg[RPW], nxt[RPW];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) rootreg[r] = P[(ly_base + r) * kTileW + lane] & kM;
-    if (kCodes) proot = P[proot] & kM;
-    for (uint32_t n = 0;; ++n) {
-        bool moved = false;
+    for (int r = 0; r < RPW; ++r) rootreg[r] = P[(ly_base + r) * kTileW + lane];
+    if (kCodes) proot = P[proot];
+    for (uint32_t n = 0;; n += 2) {
+        uint64_t moved = 0;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const uint32_t up = P[rootreg[r]] & kM;
-            moved = moved || up != rootreg[r];
-            rootreg[r] = up;
+            nxt[r] = P[rootreg[r]];
+            moved |= __ballot(nxt[r] != rootreg[r]);
+        }
+        uint32_t pnxt = 0;
+        if (kCodes) {
+            pnxt = P[proot];
+            moved |= __ballot(pnxt != proot);
+        }
+        if (moved == 0ull) break;
+        moved = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            rootreg[r] = P[nxt[r]];
+            moved |= __ballot(rootreg[r] != nxt[r]);
         }
         if (kCodes) {
-            const uint32_t up = P[proot] & kM;
-            moved = moved || up != proot;
-            proot = up;
+            proot = P[pnxt];
+            moved |= __ballot(proot != pnxt);
         }
-        if (__ballot(moved) == 0ull) break;
+        if (moved == 0ull) break;
         if (n >= kLdsWalkCap) {
             record_fault(a.ctl, kFaultLds);
             break;
@@ -761,20 +777,31 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         __syncthreads();
         // Codes: the new value of an inner component's sites, or the slot of
         // the node (and, clock, the old value) of a perimeter component's.
+        // (Potts: the low half of a root's record is the code itself, the
+        // mark being the node bit.)  Row pointers advance by L.
+        const uint32_t rb0 = __umul24(y_base, L) + static_cast<uint32_t>(x0);
+        uint16_t* crow = a.codes + rb0;
+        uint32_t* lrow = a.lroot + rb0;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int y = y_base + r;
-            if (!(kFull || (col_ok && y < L))) continue;
-            const uint32_t rec = P[rootreg[r]] & 0xFFFFu;
-            uint32_t code;
-            const int old = kClock ? static_cast<int>(sh.sp[(ly_base + r) * kTileW + lane]) : 0;
-            if (rec & kMarkPerimeter)
-                code = kCodeNode | (kClock ? static_cast<uint32_t>(old) << 8 : 0u) | (rec & 0xFFu);
-            else
-                code = kClock ? static_cast<uint32_t>(flipped<true>(rec, old, m_cur, q)) : rec;
-            const uint32_t rb = __umul24(y, L) + static_cast<uint32_t>(x0);
-            (a.codes + rb)[ulane] = static_cast<uint16_t>(code);
-            if (a.lroot) (a.lroot + rb)[ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
+            if (kFull || (col_ok && y < L)) {
+                uint32_t code;
+                if (kClock) {
+                    const uint32_t rec = P[rootreg[r]] & 0xFFFFu;
+                    const int old = static_cast<int>(sh.sp[(ly_base + r) * kTileW + lane]);
+                    if (rec & kMarkPerimeter)
+                        code = kCodeNode | (static_cast<uint32_t>(old) << 8) | (rec & 0xFFu);
+                    else
+                        code = static_cast<uint32_t>(flipped<true>(rec, old, m_cur, q));
+                } else {
+                    code = P16[2 * rootreg[r]];
+                }
+                crow[ulane] = static_cast<uint16_t>(code);
+                if (a.lroot) lrow[ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
+            }
+            crow += L;
+            lrow += L;
         }
         return;
     }
