@@ -1022,7 +1022,8 @@ __device__ __forceinline__ bool wave_first(bool want, uint32_t ka, uint32_t kb) 
     uint64_t m = __ballot(want);
     while (m) {
         const int j = __ffsll(static_cast<unsigned long long>(m)) - 1;
-        const uint32_t ja = __shfl(ka, j, 64), jb = __shfl(kb, j, 64);
+        // (j is uniform: lane reads, not a permute through LDS)
+        const uint32_t ja = __builtin_amdgcn_readlane(ka, j), jb = __builtin_amdgcn_readlane(kb, j);
         if (want && lane > static_cast<uint32_t>(j) && ka == ja && kb == jb) want = false;
         m &= __ballot(want) & ~((2ull << j) - 1ull);
     }
