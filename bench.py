@@ -541,8 +541,8 @@ def main() -> int:
                                                       "plain_spin_updates_per_s", "batched_s", "plain_s")}
         out["batched_vs_plain"]["sweeps"] = bargs.steps
         if not args.no_serve:
-            # the first 400 requests of the trace, served against one lattice per launch
-            sargs = argparse.Namespace(requests=400, budget_gib=args.budget_gib, slots=args.slots,
+            # the whole request trace (2000 requests), served against one lattice per launch
+            sargs = argparse.Namespace(requests=args.requests, budget_gib=args.budget_gib, slots=args.slots,
                                        sweeps_per_step=args.sweeps_per_step)
             ss = bench_serve(sargs)
             out["served_vs_plain"] = {"value": ss["value"], "config": ss["config"],
