@@ -33,10 +33,14 @@
  *       P(a,b,m) = [cos(2pi(a-b)/q) - cos(2pi(a+b-m)/q)] / 2.
  *   R5  Canonical label = smallest site index of the cluster (the paper's
  *       "proper label" is the smallest label, Sec. 2).
- *   R6  Flip: W = word 0 of the draw (purpose 2, c0 = canonical label).
- *       Potts: new value qmap(W) uniform over all q values, the old value
- *       included (Sec. 2, step (vi)).  Clock: the cluster is reflected iff
- *       W >= 2^31 (probability 1/2).
+ *   R6  Flip: each cluster draws at its canonical label rho (purpose 2).
+ *       Potts q >= 3: W = word 0 of the draw with c0 = rho; new value qmap(W),
+ *       uniform over all q values, the old value included (Sec. 2, step
+ *       (vi)).  The two-outcome cases take one bit B: bit (rho mod 128) of the
+ *       draw with c0 = rho div 128 (word k of a draw holds bits 32k to
+ *       32k + 31, least significant first).  Potts q = 2: new value B (the
+ *       same map, qmap(B * 2^31, 2) = B).  Clock: the cluster is reflected
+ *       iff B = 1 (probability 1/2).
  *   R7  Random start: s_i = qmap(word 0 of purpose 4, c0 = i, t = 0).
  *   R8  qmap(w) = (w * q) >> 32 in 64-bit arithmetic.
  */
@@ -301,6 +305,20 @@ void or_label(int L, const uint8_t* bond_r, const uint8_t* bond_d, int32_t* labe
 /* ------------------------------------------------------------------ */
 /* Step 3: spin flip, Sec. 2 steps (v)-(vii) (R6).                          */
 /* ------------------------------------------------------------------ */
+/* R6: the word W that decides the new value of the cluster with canonical
+ * label rho.  Two-outcome cases (Potts q = 2, the clock reflection): the
+ * cluster's bit B, given as W = B * 2^31; otherwise word 0 of its draw. */
+static uint32_t cluster_word(int q, int model, uint64_t seed, uint32_t rho, uint64_t t) {
+    uint32_t w[4];
+    if (model == OR_CLOCK || q == 2) {
+        or_draw(seed, rho >> 7, t, OR_P_CLUSTER, w);
+        const uint32_t bit = (w[(rho & 127u) >> 5] >> (rho & 31u)) & 1u;
+        return bit << 31;
+    }
+    or_draw(seed, rho, t, OR_P_CLUSTER, w);
+    return w[0];
+}
+
 /* New value of a site with old value s in a cluster whose draw is W. */
 static int8_t flip_value(int q, int model, int m, uint32_t W, int8_t s) {
     if (model == OR_POTTS) return (int8_t)or_qmap(W, (uint32_t)q);
@@ -313,26 +331,19 @@ void or_flip(int L, int q, int model, uint64_t seed, uint64_t t, const int32_t* 
     int64_t N = (int64_t)L * L;
     int m = (model == OR_CLOCK) ? or_mirror(q, seed, t) : 0;
     /* One draw per cluster, made at the cluster's proper label. */
-    uint32_t* cluster_word = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
+    uint32_t* cluster_word_of = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
     for (int64_t i = 0; i < N; ++i) {
-        if (label[i] == i) {
-            uint32_t w[4];
-            or_draw(seed, (uint32_t)i, t, OR_P_CLUSTER, w);
-            cluster_word[i] = w[0];
-        }
+        if (label[i] == i) cluster_word_of[i] = cluster_word(q, model, seed, (uint32_t)i, t);
     }
-    for (int64_t i = 0; i < N; ++i) spins[i] = flip_value(q, model, m, cluster_word[label[i]], spins[i]);
-    free(cluster_word);
+    for (int64_t i = 0; i < N; ++i) spins[i] = flip_value(q, model, m, cluster_word_of[label[i]], spins[i]);
+    free(cluster_word_of);
 }
 
 void or_flip_at(int q, int model, uint64_t seed, uint64_t t, int64_t n, const int32_t* root,
                 const int8_t* old, int8_t* out) {
     int m = (model == OR_CLOCK) ? or_mirror(q, seed, t) : 0;
-    for (int64_t k = 0; k < n; ++k) {
-        uint32_t w[4];
-        or_draw(seed, (uint32_t)root[k], t, OR_P_CLUSTER, w);
-        out[k] = flip_value(q, model, m, w[0], old[k]);
-    }
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = flip_value(q, model, m, cluster_word(q, model, seed, (uint32_t)root[k], t), old[k]);
 }
 
 int64_t or_sweep(int L, int q, int model, const uint32_t* table, uint64_t seed, uint64_t t,

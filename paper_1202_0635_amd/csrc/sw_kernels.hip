@@ -202,6 +202,18 @@ __device__ __forceinline__ int mirror_of(uint64_t t, int q, uint32_t k0, uint32_
     return static_cast<int>(qmap(draw(0u, t, kMirror, k0, k1).w0, static_cast<uint32_t>(q)));
 }
 
+// The cluster draw of canonical label rho (Sec. 2 step (vi); the paper draws
+// a new value for every label).  Potts q >= 3: qmap of word 0 of the draw
+// with c0 = rho.  Two outcomes (Potts q = 2: the new value; clock: reflect or
+// not): one bit, bit rho mod 128 of the draw with c0 = rho div 128 (word k
+// holds bits 32k .. 32k + 31), so one draw serves 128 consecutive sites.
+__device__ __forceinline__ bool two_outcomes(int model, int q) { return model == 1 || q == 2; }
+__device__ __forceinline__ uint32_t group_bit(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t rho) {
+    const uint32_t k = (rho >> 5) & 3u;
+    const uint32_t word = (k == 0) ? w0 : (k == 1) ? w1 : (k == 2) ? w2 : w3;
+    return (word >> (rho & 31u)) & 1u;
+}
+
 
 // ---------------------------------------------------------------------------
 // Bonds that leave a tile (or wrap around the torus), read from the tiles'
@@ -763,16 +775,37 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         }
         __builtin_amdgcn_wave_barrier();  // the list is read by other lanes of this wave only
         uint64_t* const nodes = a.nodes + tile * kSlotsPerTile;
-        for (uint32_t j = ulane; j < nroots; j += 64) {
-            const uint32_t root = P16[2 * (list0 + j) + 1] & (kLdsWalkCap - 1u);
+        // Two outcomes: lane k < 2 RPW draws the (k & 1)-th 128-site group
+        // that row ly_base + k / 2 of the tile meets, and a root reads its
+        // group's words from that lane (all lanes take part in the reads).
+        const bool one_bit = two_outcomes(kModel, q);
+        Words4 gw = {0u, 0u, 0u, 0u};
+        if (one_bit && ulane < 2u * RPW) {
+            const uint32_t rf = tile_base + __umul24(static_cast<uint32_t>(ly_base) + (ulane >> 1), L);
+            gw = draw((rf >> 7) + (ulane & 1u), t, kCluster, k0, k1);
+        }
+        for (uint32_t j0 = 0; j0 < nroots; j0 += 64) {
+            const uint32_t j = j0 + ulane;
+            const bool valid = j < nroots;
+            const uint32_t root =
+                valid ? (P16[2 * (list0 + j) + 1] & (kLdsWalkCap - 1u)) : static_cast<uint32_t>(ly_base * kTileW);
             const uint32_t gi = tile_base + __umul24(root >> 6, L) + (root & 63u);
-            const uint32_t w = draw(gi, t, kCluster, k0, k1).w0;
-            const uint32_t v = kClock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
-            const uint32_t rec = P[root];
-            if (rec & kMarkPerimeter)
-                nodes[rec & 0xFFu] = (static_cast<uint64_t>(gi) << 32) | kNodeRoot | v;
-            else
-                P16[2 * root] = static_cast<uint16_t>(v);
+            uint32_t v;
+            if (one_bit) {
+                const uint32_t rf = gi - (root & 63u);  // the row's first site in the tile
+                const int src = static_cast<int>(2u * ((root >> 6) - static_cast<uint32_t>(ly_base)) + ((gi >> 7) - (rf >> 7)));
+                v = group_bit(__shfl(gw.w0, src, 64), __shfl(gw.w1, src, 64), __shfl(gw.w2, src, 64),
+                              __shfl(gw.w3, src, 64), gi);
+            } else {
+                v = valid ? qmap(draw(gi, t, kCluster, k0, k1).w0, static_cast<uint32_t>(q)) : 0u;
+            }
+            if (valid) {
+                const uint32_t rec = P[root];
+                if (rec & kMarkPerimeter)
+                    nodes[rec & 0xFFu] = (static_cast<uint64_t>(gi) << 32) | kNodeRoot | v;
+                else
+                    P16[2 * root] = static_cast<uint16_t>(v);
+            }
         }
         __syncthreads();
         // Codes: the new value of an inner component's sites, or the slot of
@@ -844,22 +877,38 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         const bool is_root = __builtin_amdgcn_inverse_ballot_w64(rm);
         // every site of the row is stored (a root gets a placeholder root word
         // that its draw below overwrites), so label lines are written whole
-        const uint32_t i = __umul24(y, L) + static_cast<uint32_t>(x);
         if (ok) (a.labels + (__umul24(y, L) + static_cast<uint32_t>(x0)))[ulane] =
             is_root ? kRootFlag : tile_base + __umul24(root >> 6, L) + (root & 63u);
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(rm >> 32),
                                                          __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(rm), 0u));
-        if (is_root) list[nroots + below] = i;
+        if (is_root) list[nroots + below] = self;
         nroots += static_cast<uint32_t>(__popcll(rm));
     }
     __builtin_amdgcn_wave_barrier();  // the list is read by other lanes of this wave only
     // Every tile-local root draws its cluster's value (Sec. 3 assigns a new
-    // value to every label index; here only roots draw, one lane per root).
-    for (uint32_t j = lane; j < nroots; j += 64) {
-        const uint32_t i = list[j];
-        const uint32_t w = draw(i, t, kCluster, k0, k1).w0;
-        const uint32_t v = kClock ? (w >> 31) : qmap(w, static_cast<uint32_t>(q));
-        a.labels[i] = kRootFlag | v;
+    // value to every label index; here only roots draw, one lane per root;
+    // two outcomes: one draw per row group, as in the code output).
+    const bool one_bit = two_outcomes(kModel, q);
+    Words4 gw = {0u, 0u, 0u, 0u};
+    if (one_bit && ulane < 2u * RPW) {
+        const uint32_t rf = tile_base + __umul24(static_cast<uint32_t>(ly_base) + (ulane >> 1), L);
+        gw = draw((rf >> 7) + (ulane & 1u), t, kCluster, k0, k1);
+    }
+    for (uint32_t j0 = 0; j0 < nroots; j0 += 64) {
+        const uint32_t j = j0 + ulane;
+        const bool valid = j < nroots;
+        const uint32_t root = valid ? list[j] : static_cast<uint32_t>(ly_base * kTileW);
+        const uint32_t i = tile_base + __umul24(root >> 6, L) + (root & 63u);
+        uint32_t v;
+        if (one_bit) {
+            const uint32_t rf = i - (root & 63u);
+            const int src = static_cast<int>(2u * ((root >> 6) - static_cast<uint32_t>(ly_base)) + ((i >> 7) - (rf >> 7)));
+            v = group_bit(__shfl(gw.w0, src, 64), __shfl(gw.w1, src, 64), __shfl(gw.w2, src, 64),
+                          __shfl(gw.w3, src, 64), i);
+        } else {
+            v = valid ? qmap(draw(i, t, kCluster, k0, k1).w0, static_cast<uint32_t>(q)) : 0u;
+        }
+        if (valid) a.labels[i] = kRootFlag | v;
     }
 }
 
@@ -2091,8 +2140,14 @@ __global__ void __launch_bounds__(256) k_le_roots(SweepArgs a) {
     if (x >= a.L) return;
     const uint32_t i = __umul24(y, a.L) + static_cast<uint32_t>(x);
     if (a.labels[i] != i) return;
-    const uint32_t w = draw(i, a.ctl->t, kCluster, a.key0, a.key1).w0;
-    a.labels[i] = kRootFlag | (a.model == 1 ? (w >> 31) : qmap(w, static_cast<uint32_t>(a.q)));
+    uint32_t v;
+    if (two_outcomes(a.model, a.q)) {
+        const Words4 w = draw(i >> 7, a.ctl->t, kCluster, a.key0, a.key1);
+        v = group_bit(w.w0, w.w1, w.w2, w.w3, i);
+    } else {
+        v = qmap(draw(i, a.ctl->t, kCluster, a.key0, a.key1).w0, static_cast<uint32_t>(a.q));
+    }
+    a.labels[i] = kRootFlag | v;
 }
 
 // The sweep index advances once nothing of the sweep reads it any more.
