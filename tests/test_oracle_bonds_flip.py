@@ -84,6 +84,27 @@ def test_potts_new_values_uniform(orc, q):
     assert abs(z) < 4.5
 
 
+def test_two_outcome_draws_independent_within_and_across_groups(orc):
+    # R6: a two-outcome cluster takes one bit of the draw of its 128-site
+    # group.  Each cluster's outcome must be fair and independent of every
+    # other cluster's: pairs of canonical labels in the same group (next
+    # site, the same bit of the next word), across a group boundary and in
+    # the same bit position of the next group give four equally likely joint
+    # outcomes.  A shared bit, a single word or a shared draw per group would
+    # fail one of them.
+    base = 128 * np.arange(0, 4000, 7, dtype=np.int64)
+    pairs = {"next site": (5, 6), "next word": (9, 41), "group boundary": (127, 128), "next group": (3, 131)}
+    for name, (da, db) in pairs.items():
+        joint = np.zeros(4)
+        for t in range(8):
+            roots = np.concatenate([base + da, base + db])
+            out = orc.flip_at(2, "potts", 77, t, roots, np.zeros(roots.size, dtype=np.int8))
+            a, b = out[: base.size].astype(int), out[base.size:].astype(int)
+            joint += np.bincount(2 * a + b, minlength=4)
+        chi2, pval = stats.chisquare(joint)
+        assert pval > 1e-4, (name, joint)
+
+
 def test_flip_is_constant_on_clusters(orc):
     L, q = 64, 3
     T = 1.0 / math.log(1.0 + math.sqrt(3.0))
