@@ -643,28 +643,29 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         // that has been lowered before is no longer a root: lowering it again
         // returns its parent, which must then be joined as well.  That check
         // of a row waits until the next row's loads are issued.
+        // (Lane sets are kept as 64-bit masks in scalar registers.)
         uint32_t lab_prev = node[0];
         uint32_t old_p = 0, tgt_p = 0, lab_p = 0;
-        bool need_p = false;
-        auto join_parent = [&](bool need, uint32_t old, uint32_t tgt, uint32_t lab) {
-            const bool bad = need && old != tgt && old != lab;
-            if (__ballot(bad)) {
-                if (bad) lds_union(P, old, lab, a.ctl);
+        uint64_t need_p = 0;
+        auto join_parent = [&](uint64_t need, uint32_t old, uint32_t tgt, uint32_t lab) {
+            const uint64_t bad = need & __ballot(old != tgt) & __ballot(old != lab);
+            if (bad) {
+                if (__builtin_amdgcn_inverse_ballot_w64(bad)) lds_union(P, old, lab, a.ctl);
             }
         };
 #pragma unroll
         for (int r = 1; r < RPW; ++r) {
             const int ly = ly_base + r;
-            const uint64_t d_above = (kFull || y0 + ly < L) ? lane64(dd_lane, r - 1) : 0ull;
-            const bool up = __builtin_amdgcn_inverse_ballot_w64(d_above);
+            const uint64_t up = (kFull || y0 + ly < L) ? lane64(dd_lane, r - 1) : 0ull;
             __builtin_amdgcn_wave_barrier();
-            if (up) atomicMin(&P[node[r]], lab_prev);
+            if (__builtin_amdgcn_inverse_ballot_w64(up)) atomicMin(&P[node[r]], lab_prev);
             __builtin_amdgcn_wave_barrier();
             const uint32_t lab = lds_load(&P[node[r]]);
             if (r > 1) join_parent(need_p, old_p, tgt_p, lab_p);
-            const bool need = up && lab_prev != lab;
+            const uint64_t need = up & __ballot(lab_prev != lab);
             uint32_t old = lab_prev;
-            if (need) old = __hip_atomic_fetch_min(&P[lab_prev], lab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (__builtin_amdgcn_inverse_ballot_w64(need))
+                old = __hip_atomic_fetch_min(&P[lab_prev], lab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             need_p = need;
             old_p = old;
             tgt_p = lab_prev;
