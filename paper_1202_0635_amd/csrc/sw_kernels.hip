@@ -419,10 +419,23 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         // tile below or row 0 through the wrap, or in a ragged tile the
         // wrapped row L), whose nodes lie in other tiles' forests.
         const uint32_t ns = min(a.nslots_prev[tile], kSlotsPerTile);
+        if (kFull) {
+            // the strip's rows through one row pointer advanced by L (a
+            // scalar base and the lane's offset per load), the row below
+            // through its own (it may wrap to row 0)
+            const uint16_t* row = a.codes_prev + (__umul24(y_base, L) + static_cast<uint32_t>(x0));
 #pragma unroll
-        for (int r = 0; r <= RPW; ++r) {
-            const uint16_t* row = a.codes_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0));
-            cw[r] = row_ok(r) ? row[ulane] : 0u;
+            for (int r = 0; r < RPW; ++r) {
+                cw[r] = row[ulane];
+                row += L;
+            }
+            cw[RPW] = (a.codes_prev + (__umul24(row_of(RPW), L) + static_cast<uint32_t>(x0)))[ulane];
+        } else {
+#pragma unroll
+            for (int r = 0; r <= RPW; ++r) {
+                const uint16_t* row = a.codes_prev + (__umul24(row_of(r), L) + static_cast<uint32_t>(x0));
+                cw[r] = row_ok(r) ? row[ulane] : 0u;
+            }
         }
         const uint32_t hc = halo_lane ? static_cast<uint32_t>(a.codes_prev[ih]) : 0u;
         const bool t_walk = threadIdx.x < ns;
