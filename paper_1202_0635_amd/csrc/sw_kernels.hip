@@ -826,9 +826,8 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         // the node (and, clock, the old value) of a perimeter component's.
         // (Potts: the low half of a root's record is the code itself, the
         // mark being the node bit.)  Row pointers advance by L.
-        const uint32_t rb0 = __umul24(y_base, L) + static_cast<uint32_t>(x0);
-        uint16_t* crow = a.codes + rb0;
-        uint32_t* lrow = a.lroot + rb0;
+        uint32_t rb = __umul24(y_base, L) + static_cast<uint32_t>(x0);
+        uint16_t* crow = a.codes + rb;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int y = y_base + r;
@@ -845,10 +844,10 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                     code = P16[2 * rootreg[r]];
                 }
                 crow[ulane] = static_cast<uint16_t>(code);
-                if (a.lroot) lrow[ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
+                if (a.lroot) a.lroot[rb + ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
             }
             crow += L;
-            lrow += L;
+            rb += static_cast<uint32_t>(L);
         }
         return;
     }
