@@ -197,6 +197,8 @@ int launch_list(sw_batch* b, int l, bool profile, uint32_t row = 0, bool verify 
     if (b->blocks[l] == 0) return SW_OK;
     BatchKernel k = kListKernel[l];
     if (l == kLFlip && verify) k = kBKFlipVerify;
+    // only the flip reads the labels of a sweep without canonical labels
+    if (l == kLFlatten && !verify) k = kBKFlattenCopies;
     const BatchLaunch bl{b->d_reps, b->d_map[l], b->d_begin[l], b->blocks[l], b->tile_waves};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {

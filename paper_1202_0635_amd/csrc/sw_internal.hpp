@@ -127,9 +127,10 @@ struct SweepArgs {
     int tile_waves;       // waves per bond-kernel workgroup: kWaves or kWavesSmall (single
                           // lattices; batched launches always use kWaves)
     int merge_tiles;      // tiles per side of a first-level merge block (1: no block level)
-    int root_copies;      // k_flatten stores the cluster's root word (not a link) at every linked
+    int root_copies;      // single lattices: k_flatten stores the cluster's root word (not a link) at every linked
                           // tile-local root: the labels then lead to a root word in at most two
-                          // loads, but no longer name the root site (off in verify mode)
+                          // loads, but no longer name the root site (off in verify mode);
+                          // batched launches pick the flatten kernel per sweep instead
     uint32_t key0, key1;
 };
 
@@ -188,8 +189,8 @@ __host__ __device__ inline uint32_t merge_blocks_x(int tiles_x, int mt) {
 
 // Batched launches: one launch covers the workgroups of every replica.
 enum BatchKernel {
-    kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge, kBKFlatten, kBKFlip, kBKFlipVerify, kBKCounts,
-    kBKCountSum, kBKHash, kBKHashSum, kNumBatchKernels
+    kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge, kBKFlatten, kBKFlattenCopies, kBKFlip, kBKFlipVerify,
+    kBKCounts, kBKCountSum, kBKHash, kBKHashSum, kNumBatchKernels
 };
 struct BatchLaunch {
     const SweepArgs* reps;  // device replica table

@@ -1375,7 +1375,7 @@ __device__ __forceinline__ void copy_root_word(uint32_t* lab, uint32_t r, uint32
     lab[r] = w;
 }
 
-__device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block) {
+__device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block, const bool copies) {
     if (!a.ctl->live) return;
     // Every kernel that reads the sweep index has finished (stream order); the
     // flip only needs the mirror recorded by k_bond_local.
@@ -1388,7 +1388,7 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
     const uint32_t pi = __shfl_up(i, 1, 64), pj = __shfl_up(j, 1, 64);
     const bool first = (threadIdx.x & 63) == 0;
     const bool do_i = b.active && (first || pi != i), do_j = b.active && (first || pj != j);
-    if (a.root_copies) {
+    if (copies) {
         // both first loads are issued together (a lane without a walk reads
         // site 0 and discards it)
         const uint32_t wi = a.labels[do_i ? i : 0u], wj = a.labels[do_j ? j : 0u];
@@ -1401,28 +1401,35 @@ __device__ __forceinline__ void flatten(const SweepArgs& a, const uint32_t block
 }
 
 // ---------------------------------------------------------------------------
-// Cluster flip.  One 64 x 64 tile per workgroup; thread t takes 16
-// consecutive sites of row t/4.  The tile's label words are staged in LDS, and
-// every step of a path whose target lies in the tile reads LDS: an ordinary
-// site's label word names its tile-local root, which is in the tile.  A
-// tile-local root that was merged across tiles holds a link (after the
-// flatten, straight to its cluster root) that may leave the tile; such steps
-// read global memory.
+// Cluster flip.  One 64 x 64 tile per workgroup, sixteen sites per thread.
+// When the lattice side is a multiple of four, thread t takes sixteen
+// consecutive sites of tile row t/4 (vector loads and stores); otherwise lane
+// l of wave v takes column l of tile rows 16v .. 16v+15, so that every access
+// of a wave is one contiguous piece of a lattice row.  The tile's label words
+// are staged in LDS, and every step of a path whose target lies in the tile
+// reads LDS: an ordinary site's label word names its tile-local root, which
+// is in the tile.  A tile-local root that was merged across tiles holds a
+// link (after the flatten, straight to its cluster root, or a copy of the
+// root word) that may leave the tile; such steps read global memory.
 // ---------------------------------------------------------------------------
-template <bool kVerify>
-__device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int ty) {
-    __shared__ uint32_t tl[kTileH * kTileW];
-    if (!a.ctl->live) return;
+template <bool kVerify, bool rows4>
+__device__ __forceinline__ void flip_tile(const SweepArgs& a, const int tx, const int ty, uint32_t* tl) {
     const int L = a.L;
-    const int ly = static_cast<int>(threadIdx.x >> 2), lx = static_cast<int>(threadIdx.x & 3) * 16;
-    const int y = ty * kTileH + ly;
-    const int xs = tx * kTileW + lx;
-    const int nx = (y < L) ? max(0, min(16, L - xs)) : 0;
     const uint32_t nrows = static_cast<uint32_t>(min(kTileH, L - ty * kTileH));
     const uint32_t ncols = static_cast<uint32_t>(min(kTileW, L - tx * kTileW));
     const uint32_t tile_base = __umul24(ty * kTileH, L) + static_cast<uint32_t>(tx * kTileW);
-    const uint32_t base = __umul24(min(y, L - 1), L) + static_cast<uint32_t>(min(xs, L - 1));
-    const bool full = (nx == 16) && ((base & 3u) == 0);
+    const uint32_t t = threadIdx.x;
+    const uint32_t ly = rows4 ? (t >> 2) : (t >> 6) * 16u;
+    const uint32_t lx = rows4 ? (t & 3u) * 16u : (t & 63u);
+    // sites k < n of the thread lie in the lattice: site k is at tile row
+    // ly + k (column mapping) or column lx + k (row mapping)
+    const uint32_t run = rows4 ? ncols : nrows, first = rows4 ? lx : ly;
+    const bool on = rows4 ? (ly < nrows) : (lx < ncols);
+    const int n = (on && first < run) ? static_cast<int>(min(16u, run - first)) : 0;
+    const uint32_t step = rows4 ? 1u : static_cast<uint32_t>(L);  // lattice index step
+    const uint32_t lstep = rows4 ? 1u : static_cast<uint32_t>(kTileW);
+    const uint32_t base = n ? tile_base + __umul24(ly, L) + lx : 0u;
+    const bool full = rows4 && n == 16;  // the row mapping's sixteen sites, 16-byte aligned words
     uint32_t x[16], w[16];
     if (full) {
 #pragma unroll
@@ -1432,10 +1439,10 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) w[k] = (k < nx) ? a.labels[base + k] : kRootFlag;
+        for (int k = 0; k < 16; ++k) w[k] = (k < n) ? a.labels[base + k * step] : kRootFlag;
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) tl[ly * kTileW + lx + k] = w[k];
+    for (int k = 0; k < 16; ++k) tl[ly * kTileW + lx + k * lstep] = w[k];
     __syncthreads();
     // First step.  A target lies in the tile when its offset d from the
     // tile's first site is below nrows * L and d mod L is below the tile's
@@ -1445,7 +1452,7 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
     const uint32_t span = nrows * static_cast<uint32_t>(L);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        x[k] = base + k;
+        x[k] = base + k * step;
         if (!(w[k] & kRootFlag)) {
             x[k] = w[k];
             const uint32_t d = w[k] - tile_base;
@@ -1463,8 +1470,8 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
     }
     // Further steps (paths through merged roots), sixteen paths together.
     bool pending = true;
-    for (uint32_t n = 0; pending; ++n) {
-        if (n >= kGlobalWalkCap) {
+    for (uint32_t m = 0; pending; ++m) {
+        if (m >= kGlobalWalkCap) {
             record_fault(a.ctl, kFaultFlip);
             break;
         }
@@ -1477,7 +1484,7 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
                 pending = true;
             }
     }
-    if (nx == 0) return;
+    if (n == 0) return;
     uint32_t out[16];
     if (a.model == 0) {
 #pragma unroll
@@ -1489,7 +1496,9 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
             const uint4 v = *reinterpret_cast<const uint4*>(a.spins + base);
             old[0] = v.x; old[1] = v.y; old[2] = v.z; old[3] = v.w;
         } else {
-            for (int k = 0; k < nx; ++k) old[k >> 2] |= static_cast<uint32_t>(static_cast<uint8_t>(a.spins[base + k])) << (8 * (k & 3));
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < n) old[k >> 2] |= static_cast<uint32_t>(static_cast<uint8_t>(a.spins[base + k * step])) << (8 * (k & 3));
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -1512,11 +1521,21 @@ __device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int
     } else {
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            if (k < nx) {
-                a.flip_out[base + k] = static_cast<int8_t>(out[k]);
-                if (kVerify) a.canon[base + k] = x[k];
+            if (k < n) {
+                a.flip_out[base + k * step] = static_cast<int8_t>(out[k]);
+                if (kVerify) a.canon[base + k * step] = x[k];
             }
     }
+}
+
+template <bool kVerify>
+__device__ __forceinline__ void flip(const SweepArgs& a, const int tx, const int ty) {
+    __shared__ uint32_t tl[kTileH * kTileW];
+    if (!a.ctl->live) return;
+    if ((a.L & 3) == 0)
+        flip_tile<kVerify, true>(a, tx, ty, tl);
+    else
+        flip_tile<kVerify, false>(a, tx, ty, tl);
 }
 
 // ---------------------------------------------------------------------------
@@ -2031,7 +2050,7 @@ __global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
     border_merge(a, border_block(a, a.merge_tiles) * blockDim.x + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, border_block(a, 1)); }
+__global__ void __launch_bounds__(256) k_flatten(SweepArgs a) { flatten(a, border_block(a, 1), a.root_copies != 0); }
 
 __global__ void __launch_bounds__(256) k_node_merge(SweepArgs a) {
     node_merge(a, border_block(a, 1) * blockDim.x + threadIdx.x);
@@ -2198,10 +2217,14 @@ __global__ void __launch_bounds__(256) kb_border_merge(BatchMap m) {
     border_merge(a, local * blockDim.x + threadIdx.x);
 }
 
+// kCopies: root copies (a sweep whose labels only the flip reads); otherwise
+// links straight to the cluster root, which a verify sweep's canonical
+// labels need.
+template <bool kCopies>
 __global__ void __launch_bounds__(256) kb_flatten(BatchMap m) {
     uint32_t local;
     const SweepArgs& a = m.reps[batch_replica(m, &local)];
-    flatten(a, local);
+    flatten(a, local, kCopies);
 }
 
 template <bool kVerify>
@@ -2418,7 +2441,8 @@ hipError_t launch_batch(BatchKernel k, const BatchLaunch& l, hipStream_t s, uint
             break;
         case kBKBlockMerge: hipLaunchKernelGGL(kb_block_merge, grid, dim3(kMergeThreads), 0, s, m); break;
         case kBKBorderMerge: hipLaunchKernelGGL(kb_border_merge, grid, dim3(256), 0, s, m); break;
-        case kBKFlatten: hipLaunchKernelGGL(kb_flatten, grid, dim3(256), 0, s, m); break;
+        case kBKFlatten: hipLaunchKernelGGL(kb_flatten<false>, grid, dim3(256), 0, s, m); break;
+        case kBKFlattenCopies: hipLaunchKernelGGL(kb_flatten<true>, grid, dim3(256), 0, s, m); break;
         case kBKFlip: hipLaunchKernelGGL(kb_flip<false>, grid, dim3(256), 0, s, m); break;
         case kBKFlipVerify: hipLaunchKernelGGL(kb_flip<true>, grid, dim3(256), 0, s, m); break;
         case kBKCounts: hipLaunchKernelGGL(kb_counts, grid, dim3(kCountThreads), count_lds_bytes(3, 1), s, m); break;

@@ -34,9 +34,10 @@ using namespace swmc::host;
 namespace {
 
 constexpr int kSweepLists[] = {kLBondPotts, kLBondClock, kLBlockMerge, kLBorderMerge, kLFlatten, kLFlip};
+// The server keeps no canonical labels: the flatten leaves root copies.
 constexpr BatchKernel kKernelOf[kNumLists] = {kBKBondPotts, kBKBondClock, kBKBlockMerge, kBKBorderMerge,
-                                              kBKFlatten,   kBKFlip,      kBKCounts,     kBKCountSum,
-                                              kBKHash,      kBKHashSum};
+                                              kBKFlattenCopies, kBKFlip, kBKCounts, kBKCountSum,
+                                              kBKHash, kBKHashSum};
 
 // Results of one retiring lattice, copied back from the device.
 struct Staging {
