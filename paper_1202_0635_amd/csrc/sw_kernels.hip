@@ -826,7 +826,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
         // the node (and, clock, the old value) of a perimeter component's.
         // (Potts: the low half of a root's record is the code itself, the
         // mark being the node bit.)  Row pointers advance by L.
-        uint32_t rb = __umul24(y_base, L) + static_cast<uint32_t>(x0);
+        const uint32_t rb = __umul24(y_base, L) + static_cast<uint32_t>(x0);
         uint16_t* crow = a.codes + rb;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
@@ -844,10 +844,17 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                     code = P16[2 * rootreg[r]];
                 }
                 crow[ulane] = static_cast<uint16_t>(code);
-                if (a.lroot) a.lroot[rb + ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
             }
             crow += L;
-            rb += static_cast<uint32_t>(L);
+        }
+        if (a.lroot) {  // (verify sweeps) every site's tile-local root
+            uint32_t* lrow = a.lroot + rb;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                if (kFull || (col_ok && y_base + r < L))
+                    lrow[ulane] = tile_base + __umul24(rootreg[r] >> 6, L) + (rootreg[r] & 63u);
+                lrow += L;
+            }
         }
         return;
     }
