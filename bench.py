@@ -545,9 +545,14 @@ def main() -> int:
             sargs = argparse.Namespace(requests=args.requests, budget_gib=args.budget_gib, slots=args.slots,
                                        sweeps_per_step=args.sweeps_per_step)
             ss = bench_serve(sargs)
+            sat = ss["saturation"]
             out["served_vs_plain"] = {"value": ss["value"], "config": ss["config"],
                                       "results_identical": ss["results_identical"],
-                                      "served": ss["served"], "plain": ss["plain"]}
+                                      "served": ss["served"], "plain": ss["plain"],
+                                      "saturation": {"makespan_s": sat["makespan_s"],
+                                                     "spin_updates_per_s": sat["spin_updates_per_s"],
+                                                     "vs_plain": sat["spin_updates_per_s"]
+                                                     / ss["plain"]["spin_updates_per_s"]}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
