@@ -54,6 +54,36 @@ __device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Lane k of v takes the wave-uniform value s: one VALU instruction, no
+// branch on the lane.  The lane is an immediate (with the value in a scalar
+// register it is the instruction's one scalar operand), so k must fold to a
+// constant below 16, as an unrolled loop index does; the switch then folds.
+template <int K>
+__device__ __forceinline__ void write_lane_k(uint32_t& v, uint32_t s) {
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(s), "i"(K));
+}
+__device__ __forceinline__ void write_lane(uint32_t& v, uint32_t s, int k) {
+    switch (k) {
+        case 0: write_lane_k<0>(v, s); break;
+        case 1: write_lane_k<1>(v, s); break;
+        case 2: write_lane_k<2>(v, s); break;
+        case 3: write_lane_k<3>(v, s); break;
+        case 4: write_lane_k<4>(v, s); break;
+        case 5: write_lane_k<5>(v, s); break;
+        case 6: write_lane_k<6>(v, s); break;
+        case 7: write_lane_k<7>(v, s); break;
+        case 8: write_lane_k<8>(v, s); break;
+        case 9: write_lane_k<9>(v, s); break;
+        case 10: write_lane_k<10>(v, s); break;
+        case 11: write_lane_k<11>(v, s); break;
+        case 12: write_lane_k<12>(v, s); break;
+        case 13: write_lane_k<13>(v, s); break;
+        case 14: write_lane_k<14>(v, s); break;
+        case 15: write_lane_k<15>(v, s); break;
+        default: break;
+    }
+}
+
 // A walk that has taken more steps than its forest has nodes has met a broken
 // forest (links must point to smaller indices): it records a fault bit in the
 // control block and stops, so a kernel ends instead of looping.
@@ -329,6 +359,7 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     constexpr bool kFused = kSrc == kFromCodes;
     constexpr int RPW = kTileH / kW;  // rows per wave (kW waves per tile)
     static_assert(RPW % 8 == 0, "a wave's rows must be whole 8-row draw groups");
+    static_assert(RPW <= 16, "phase 1 gathers a wave's row masks in lanes 0 .. 15");
     uint32_t* const P = sh.P;
     uint64_t* const raw_r = sh.raw_r;
     uint64_t* const raw_d = sh.raw_d;
@@ -519,6 +550,9 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
     for (int k = 0; k < RPW / 4; ++k) hv[k] = *reinterpret_cast<const uint32_t*>(&halo[ly_base + 4 * k]);
     const uint32_t chi = c_eq >> 24;                    // Potts: high byte of the cutoff
     const bool lo_matters = (c_eq & 0xFFFFFFu) != 0u;   // ties need the low 24 bits
+    // the strip's row masks gather in lanes: lane r holds row r's (low and
+    // high halves, right and down bonds), stored to LDS after the loop
+    uint32_t mrl = 0u, mrh = 0u, mdl = 0u, mdh = 0u;
 #pragma unroll
     for (int g = 0; g < RPW / 8; ++g) {
         const int ly0 = ly_base + g * 8;
@@ -555,15 +589,19 @@ __device__ __forceinline__ void bond_local_tile(const SweepArgs& a, const int tx
                 tr = lo_matters && ok && (s == sr) && (hr == chi);
                 td = lo_matters && ok && (s == sd) && (hd == chi);
             }
-            if (lane == 0) {
-                raw_r[ly] = mr;
-                raw_d[ly] = md;
-            }
+            write_lane(mrl, static_cast<uint32_t>(mr), r);
+            write_lane(mrh, static_cast<uint32_t>(mr >> 32), r);
+            write_lane(mdl, static_cast<uint32_t>(md), r);
+            write_lane(mdh, static_cast<uint32_t>(md >> 32), r);
             if (tr || td) {
                 const uint32_t pos = atomicAdd(&ntie, 1u);
                 P[pos] = static_cast<uint32_t>(ly * kTileW + lane) | (tr ? 1u << 12 : 0u) | (td ? 1u << 13 : 0u);
             }
         }
+    }
+    if (lane < RPW) {
+        raw_r[ly_base + lane] = (static_cast<uint64_t>(mrh) << 32) | mrl;
+        raw_d[ly_base + lane] = (static_cast<uint64_t>(mdh) << 32) | mdl;
     }
     __syncthreads();
 
