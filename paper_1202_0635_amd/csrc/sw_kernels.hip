@@ -2073,7 +2073,9 @@ __global__ void __launch_bounds__(kMergeThreads) k_block_merge(SweepArgs a) { bl
 // contiguous band of rows of the vertical borders and one contiguous run of
 // the horizontal ones: the rows whose labels the bond kernel wrote on that
 // XCD (tiles are numbered so that each XCD labels one contiguous run of tile
-// rows), so the label loads of the walks tend to hit its L2.
+// rows), so the label loads of the walks tend to hit its L2.  The
+// horizontal borders' workgroups are dispatched first: their walks are the
+// longer ones (measured), and the vertical ones fill in behind them.
 __device__ __forceinline__ uint32_t border_block(const SweepArgs& a, int step) {
     const uint32_t b = blockIdx.x, n = gridDim.x;
     const uint32_t L = static_cast<uint32_t>(a.L);
@@ -2083,12 +2085,12 @@ __device__ __forceinline__ uint32_t border_block(const SweepArgs& a, int step) {
     const uint32_t bands = L / 256u;
     const uint32_t nv = nvb * bands, nh = nhb * bands;
     if (n != nv + nh || nv % kXcds || nh % kXcds) return b;
-    const uint32_t x = b % kXcds, i = b / kXcds, cv = nv / kXcds;
-    if (i < cv) {
-        const uint32_t v = x * cv + i;  // band-major: band v / nvb, border v % nvb
+    const uint32_t x = b % kXcds, i = b / kXcds, cv = nv / kXcds, ch = nh / kXcds;
+    if (i >= ch) {
+        const uint32_t v = x * cv + (i - ch);  // band-major: band v / nvb, border v % nvb
         return (v % nvb) * bands + v / nvb;
     }
-    return nv + x * (nh / kXcds) + (i - cv);
+    return nv + x * ch + i;
 }
 
 __global__ void __launch_bounds__(256) k_border_merge(SweepArgs a) {
