@@ -75,16 +75,19 @@ def test_static_sweeps_equal_context_sweeps(swmc):
 def test_static_sweep_without_labels_and_zero_sweeps(swmc):
     import torch
 
-    L, q, model, T, seed = 200, 4, "potts", 0.9102392266268373, 24
-    start, want_s, _ = _reference(swmc, L, q, model, T, seed, 2, 5)
-    spins = torch.from_numpy(start.reshape(-1).copy()).to("cuda")
-    table = torch.from_numpy(swmc.cutoff_table(L, q, model, T).view(np.int32)).to("cuda")
-    swmc.sweep_static(spins, L, q, model, T=T, seed=seed, t=2, nsweeps=0, table=table)
-    torch.cuda.synchronize()
-    assert np.array_equal(spins.cpu().numpy().reshape(L, L), start)
-    swmc.sweep_static(spins, L, q, model, T=T, seed=seed, t=2, nsweeps=5, table=table)
-    torch.cuda.synchronize()
-    assert np.array_equal(spins.cpu().numpy().reshape(L, L), want_s)
+    # without labels the flatten leaves root copies; L = 131 (odd side) takes
+    # the flip's column-per-lane layout
+    for (L, q, model, T, seed) in ((200, 4, "potts", 0.9102392266268373, 24), (131, 6, "clock", 0.9, 25)):
+        _say(f"[no-alloc] no labels L={L} q={q} {model}")
+        start, want_s, _ = _reference(swmc, L, q, model, T, seed, 2, 5)
+        spins = torch.from_numpy(start.reshape(-1).copy()).to("cuda")
+        table = torch.from_numpy(swmc.cutoff_table(L, q, model, T).view(np.int32)).to("cuda")
+        swmc.sweep_static(spins, L, q, model, T=T, seed=seed, t=2, nsweeps=0, table=table)
+        torch.cuda.synchronize()
+        assert np.array_equal(spins.cpu().numpy().reshape(L, L), start)
+        swmc.sweep_static(spins, L, q, model, T=T, seed=seed, t=2, nsweeps=5, table=table)
+        torch.cuda.synchronize()
+        assert np.array_equal(spins.cpu().numpy().reshape(L, L), want_s), f"L={L}: spins differ"
 
 
 def test_static_rejects_beyond_maximum(swmc):
