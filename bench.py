@@ -318,11 +318,15 @@ def bench_uscan(args) -> dict:
     import paper_1202_0635_amd as swmc
 
     sizes = [int(v) for v in args.uscan_sizes.split(",")]
-    therm, meas, w = args.uscan_therm, args.uscan_sweeps, args.uscan_width
+    therm, w = args.uscan_therm, args.uscan_width
     potts_grid = [1.0 - w + 0.25 * w * k for k in range(9)]  # T / T_c
+    wanted = set(args.uscan_models.split(","))
     models = []
-    for q, model, grid in ((2, "potts", potts_grid), (3, "potts", potts_grid),
-                           (6, "clock", [0.6 + 0.0625 * k for k in range(9)])):
+    for name, q, model, grid in (("potts2", 2, "potts", potts_grid), ("potts3", 3, "potts", potts_grid),
+                                 ("clock6", 6, "clock", [0.6 + 0.0625 * k for k in range(9)])):
+        if name not in wanted:
+            continue
+        meas = args.uscan_sweeps if (model == "potts" or args.uscan_clock_sweeps is None) else args.uscan_clock_sweeps
         tc = swmc.critical_temperature(model, q)
         temps = [tc * f for f in grid] if model == "potts" else list(grid)
         specs = [(L, q, model, T, 1.0, 0x600000 + 1000 * L + k) for L in sizes for k, T in enumerate(temps)]
@@ -342,7 +346,7 @@ def bench_uscan(args) -> dict:
         curves = {L: [obs[i * len(temps) + k][key] for k in range(len(temps))] for i, L in enumerate(sizes)}
         row = {"model": model, "q": q, "observable": "U" if model == "potts" else "R", "T": temps,
                "curves": {str(L): c for L, c in curves.items()}, "seconds": dt,
-               "spin_updates": sum(L * L for L in sizes) * len(temps) * (therm + meas)}
+               "measured_sweeps": meas, "spin_updates": sum(L * L for L in sizes) * len(temps) * (therm + meas)}
         if model == "potts":
             row["T_c_exact"] = tc
             row["crossings"] = crossings(temps, curves)
@@ -350,8 +354,8 @@ def bench_uscan(args) -> dict:
         models.append(row)
     return {"metric": "moment ratio U(T) and correlation ratio R(T) scans", "value": None, "unit": None,
             "higher_is_better": None, "n_gpus": 1, "dtype": "int8", "data": "synthetic",
-            "config": {"workload": "uscan_potts2_potts3_clock6", "sizes": sizes, "therm_sweeps": therm,
-                       "measured_sweeps": meas, "potts_grid_half_width": w},
+            "config": {"workload": "uscan_" + "_".join(m for m in ("potts2", "potts3", "clock6") if m in wanted),
+                       "sizes": sizes, "therm_sweeps": therm, "potts_grid_half_width": w},
             "models": models}
 
 
@@ -399,6 +403,9 @@ def main() -> int:
     ap.add_argument("--uscan-therm", type=int, default=2000)
     ap.add_argument("--uscan-sweeps", type=int, default=20000)
     ap.add_argument("--uscan-width", type=float, default=0.03, help="Potts grid: T/T_c from 1 - w to 1 + w")
+    ap.add_argument("--uscan-models", default="potts2,potts3,clock6", help="comma list of potts2, potts3, clock6")
+    ap.add_argument("--uscan-clock-sweeps", type=int, default=None,
+                    help="measured sweeps of the clock model (default: --uscan-sweeps)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
