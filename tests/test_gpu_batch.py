@@ -86,6 +86,37 @@ def test_batch_replicas_follow_their_own_chains(swmc, orc, graph):
     b.close()
 
 
+# Sides whose rows are not a multiple of four sites: the flip takes one
+# column of sixteen rows per lane there (sixteen consecutive sites of a row
+# per thread otherwise).  Sides below a tile, one or two sites past it, and
+# every residue mod 4; the clock replicas read the old spins in that layout.
+ODD_SIDES = [
+    (3, 2, "potts", TC2, 1.0, 31),
+    (5, 6, "clock", 0.9, 1.0, 32),
+    (7, 3, "potts", TC3, 1.0, 33),
+    (17, 4, "potts", 0.9, 1.0, 34),
+    (63, 6, "clock", 0.8, 1.0, 35),
+    (66, 2, "potts", TC2, 1.0, 36),
+    (67, 6, "clock", 1.0, 1.0, 37),
+    (129, 3, "potts", TC3, 1.0, 38),
+    (131, 2, "clock", 1.1, 1.0, 39),
+]
+
+
+def test_batch_odd_sides_follow_the_oracle_every_sweep(swmc, orc):
+    _say("[batch] odd sides, one sweep per call")
+    b = swmc.Batch(ODD_SIDES)
+    chains = [orc.Chain(L, q, model, T=T, J=J, seed=seed) for (L, q, model, T, J, seed) in ODD_SIDES]
+    for t in range(1, 7):
+        b.sweep(1, verify=(t % 3 == 0), graph=False)
+        for r, ch in enumerate(chains):
+            ch.sweep(1)
+            assert np.array_equal(b.spins(r).reshape(-1), ch.spins), f"replica {r} (L={ODD_SIDES[r][0]}) spins, sweep {t}"
+            if t % 3 == 0:
+                assert np.array_equal(b.labels(r).reshape(-1), ch.labels), f"replica {r} labels, sweep {t}"
+    b.close()
+
+
 def test_batch_equals_alone_and_measures(swmc, orc):
     specs = [(96, 3, "potts", TC3 * (0.9 + 0.2 * r / 7), 1.0, 0x4000 + r) for r in range(8)]
     _say("[batch] measure")
